@@ -1,0 +1,508 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU oracle of one D2Q9 multiphase lattice
+ * Boltzmann time step, for the two models compared in Czelusniak et al.,
+ * "Fundamental comparison between the pseudopotential and the free energy
+ * lattice Boltzmann methods" (arXiv 2403.11167):
+ *
+ *   model 0  modified pseudopotential (MP-LBM): Shan-Chen force (Eq. 10)
+ *            with the Yuan-Schaefer potential (Eq. 11), Li's consistency
+ *            forcing scaled by kappa^P (Eq. 32), source term (Eq. 13) with
+ *            the width-controlling Q tensor (Eq. 30-31);
+ *   model 1  improved well-balanced free energy (IWB-FE-LBM): equilibrium
+ *            (Eq. 20) and forcing (Eq. 21) with A = 0 and p_g = 0, chemical
+ *            potential mu = mu_b - kappa lap(rho) (Sec. 2.2) and the
+ *            9-point stencils of Eq. 24.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file exists so that the GPU path can be
+ * checked against something slow and obviously correct.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it;
+ * the product library never links or calls it.  It shares no code, header,
+ * table or constant with the GPU path.
+ *
+ * Style rules followed on purpose:
+ *   - FP64 everywhere, compiled with -ffp-contract=off (no fused multiply-add);
+ *   - equilibria and the free-energy forcing are built in velocity space,
+ *     then mapped to moments with explicit 9x9 products by M (Eq. 48);
+ *     post-collision populations come back through the printed M^-1 (Eq. 49);
+ *   - every node's quantities are computed from full-field arrays in separate
+ *     sweeps (density, then potential / chemical potential, then the
+ *     per-node collision), so that a reader can follow the paper by eye.
+ *
+ * Readings of the paper adopted here (where it is ambiguous or garbled):
+ *   R1  C_2 = (G/2)(1 - kappa^P)  (Eq. 31b printed without G; App. C Eq. 41b
+ *       and App. E Eq. 76 both require the factor G).
+ *   R2  The gradient stencil of Eq. 24 carries the weights w_i (stated in the
+ *       sentence after Eq. 24, and needed for App. D Eq. 59-60).
+ *   R3  |F_int|^2 / psi^2 is evaluated as G^2 |S|^2 with S the neighbour sum
+ *       of Eq. 10, which is the same number and is finite where psi = 0.
+ *   R4  psi^2 < 0 (an equation of state above rho c_s^2) is clamped to zero
+ *       and reported through a sticky flag.
+ *   R5  Within a step, forces use the density of the populations at the start
+ *       of the step; all densities are formed before any collision.
+ *   R6  The forcing term of Eq. 32 uses the total force F = F_int + F_b,
+ *       with F_b a constant body force (zero in all standard workloads);
+ *       the consistency term uses F_int only.  For the free-energy model the
+ *       total force is -rho grad(mu) + F_b.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MODEL_P 0
+#define ORC_MODEL_FE 1
+#define ORC_EOS_VDW 0
+#define ORC_EOS_CS 1
+
+#define ORC_FLAG_NONFINITE 1u
+#define ORC_FLAG_PSI_CLAMP 2u
+#define ORC_FLAG_EOS_DOMAIN 4u
+
+typedef struct {
+  int32_t nx, ny;
+  int32_t model; /* ORC_MODEL_P or ORC_MODEL_FE */
+  int32_t eos;   /* ORC_EOS_VDW or ORC_EOS_CS */
+  double a, b, R, T;
+  double tau[9]; /* one relaxation time per moment row (Eq. 3) */
+  double sigma_li, kappa_li, kappa_p; /* pseudopotential only */
+  double kappa;                       /* free energy only */
+  double fx, fy;                      /* constant body force */
+} orc_params;
+
+/* ---- lattice (Eq. 2 and the weights stated under Eq. 4) ------------------ */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double WGT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                              1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const double CS2 = 1.0 / 3.0; /* c_s^2 for c = 1 */
+static const double G = -1.0;        /* interaction sign chosen after Eq. 11 */
+
+/* Shan-Chen weights omega(|c|^2) of Eq. 10: 1/3 for |c|^2 = 1, 1/12 for 2. */
+static double omega_sc(int i) {
+  int c2 = CX[i] * CX[i] + CY[i] * CY[i];
+  if (c2 == 1) return 1.0 / 3.0;
+  if (c2 == 2) return 1.0 / 12.0;
+  return 0.0;
+}
+
+/* ---- moment matrices: M of Eq. 48 and M^-1 as printed in Eq. 49 ---------- */
+static const double MM[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},          {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},      {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},       {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},       {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+static const double MINV[9][9] = {
+    {1. / 9, -1. / 9, 1. / 9, 0, 0, 0, 0, 0, 0},
+    {1. / 9, -1. / 36, -1. / 18, 1. / 6, -1. / 6, 0, 0, 1. / 4, 0},
+    {1. / 9, -1. / 36, -1. / 18, 0, 0, 1. / 6, -1. / 6, -1. / 4, 0},
+    {1. / 9, -1. / 36, -1. / 18, -1. / 6, 1. / 6, 0, 0, 1. / 4, 0},
+    {1. / 9, -1. / 36, -1. / 18, 0, 0, -1. / 6, 1. / 6, -1. / 4, 0},
+    {1. / 9, 1. / 18, 1. / 36, 1. / 6, 1. / 12, 1. / 6, 1. / 12, 0, 1. / 4},
+    {1. / 9, 1. / 18, 1. / 36, -1. / 6, -1. / 12, 1. / 6, 1. / 12, 0, -1. / 4},
+    {1. / 9, 1. / 18, 1. / 36, -1. / 6, -1. / 12, -1. / 6, -1. / 12, 0, 1. / 4},
+    {1. / 9, 1. / 18, 1. / 36, 1. / 6, 1. / 12, -1. / 6, -1. / 12, 0, -1. / 4}};
+
+static void mat_vec(const double A[9][9], const double *v, double *out) {
+  for (int r = 0; r < 9; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < 9; ++c) s += A[r][c] * v[c];
+    out[r] = s;
+  }
+}
+
+/* ---- equations of state -------------------------------------------------- */
+/* Carnahan-Starling, Eq. 28; van der Waals p = rho R T/(1 - b rho) - a rho^2. */
+static double eos_pressure(const orc_params *p, double rho) {
+  if (p->eos == ORC_EOS_CS) {
+    double e = p->b * rho / 4.0;
+    double num = 1.0 + e + e * e - e * e * e;
+    double den = (1.0 - e) * (1.0 - e) * (1.0 - e);
+    return rho * p->R * p->T * num / den - p->a * rho * rho;
+  }
+  return rho * p->R * p->T / (1.0 - p->b * rho) - p->a * rho * rho;
+}
+
+/* Bulk chemical potential.  Carnahan-Starling: Eq. 29.  Van der Waals: the
+ * antiderivative of (1/rho) dp/drho (the relation -rho d(mu_b) = -dp of
+ * Sec. 2.2), RT ln(rho/(1-b rho)) + RT b rho/(1-b rho) - 2 a rho.          */
+static double eos_mu_b(const orc_params *p, double rho) {
+  double RT = p->R * p->T;
+  if (p->eos == ORC_EOS_CS) {
+    double e = p->b * rho / 4.0;
+    return RT * (3.0 - e) / ((1.0 - e) * (1.0 - e) * (1.0 - e)) +
+           RT * log(rho) + RT - 2.0 * p->a * rho;
+  }
+  return RT * log(rho / (1.0 - p->b * rho)) +
+         RT * p->b * rho / (1.0 - p->b * rho) - 2.0 * p->a * rho;
+}
+
+static int eos_domain_ok(const orc_params *p, double rho) {
+  double lim = (p->eos == ORC_EOS_CS) ? p->b * rho / 4.0 : p->b * rho;
+  if (!(lim < 1.0)) return 0;
+  if (p->model == ORC_MODEL_FE && !(rho > 0.0)) return 0;
+  return 1;
+}
+
+/* Yuan-Schaefer potential, Eq. 11 with G = -1 and c = dt = 1:
+ * psi = sqrt(2 (p_EOS - rho c_s^2) / G).  Negative argument -> clamp (R4). */
+static double psi_of_rho(const orc_params *p, double rho, unsigned *flags) {
+  double arg = 2.0 * (eos_pressure(p, rho) - rho * CS2) / G;
+  if (arg < 0.0) {
+    *flags |= ORC_FLAG_PSI_CLAMP;
+    arg = 0.0;
+  }
+  return sqrt(arg);
+}
+
+/* ---- equilibria in velocity space ---------------------------------------- */
+/* Eq. 4 (pseudopotential). */
+static void feq_standard(double rho, double ux, double uy, double *feq) {
+  for (int i = 0; i < 9; ++i) {
+    double cu = CX[i] * ux + CY[i] * uy;
+    double uu = ux * ux + uy * uy;
+    double quad = (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2);
+    feq[i] = WGT[i] * rho * (1.0 + cu / CS2 + quad);
+  }
+}
+
+/* Eq. 20 with p_g = 0 and A = 0 (free energy); c_s^4 in the i != 0 term as
+ * printed in Eq. 20. */
+static void feq_well_balanced(double rho, double ux, double uy, double *feq) {
+  double uu = ux * ux + uy * uy;
+  feq[0] = rho - WGT[0] * rho * uu / (2.0 * CS2);
+  for (int i = 1; i < 9; ++i) {
+    double cu = CX[i] * ux + CY[i] * uy;
+    double quad = (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2);
+    feq[i] = WGT[i] * rho * (cu / CS2 + quad);
+  }
+}
+
+/* Eq. 21 with p_g = 0, d = 2: velocity-space forcing of the free-energy
+ * model, with gx, gy the stencil gradient of rho. */
+static void forcing_well_balanced(double ux, double uy, double Fx, double Fy,
+                                  double gx, double gy, double *Fi) {
+  double Bx = Fx + CS2 * gx, By = Fy + CS2 * gy;
+  double ug = ux * gx + uy * gy;
+  for (int i = 0; i < 9; ++i) {
+    double cF = CX[i] * Fx + CY[i] * Fy;
+    /* (c_a c_b - c_s^2 delta_ab) u_a B_b */
+    double cu = CX[i] * ux + CY[i] * uy;
+    double cB = CX[i] * Bx + CY[i] * By;
+    double second = cu * cB - CS2 * (ux * Bx + uy * By);
+    double c2 = (double)(CX[i] * CX[i] + CY[i] * CY[i]);
+    Fi[i] = WGT[i] * (cF / CS2 + second / (CS2 * CS2) +
+                      0.5 * (c2 / CS2 - 2.0) * ug);
+  }
+}
+
+static int wrap(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+/* ---- stencils on a periodic field (exposed for unit tests) --------------- */
+
+/* Shan-Chen neighbour sum S_a = sum_{i=1..8} omega_i phi(x+c_i) c_ia, so that
+ * Eq. 10 reads F_a = -G psi(x) S_a. */
+void orc_sc_sum(int nx, int ny, const double *phi, double *Sx, double *Sy) {
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double sx = 0.0, sy = 0.0;
+      for (int i = 1; i < 9; ++i) {
+        double v = phi[wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)];
+        sx += omega_sc(i) * v * CX[i];
+        sy += omega_sc(i) * v * CY[i];
+      }
+      Sx[y * nx + x] = sx;
+      Sy[y * nx + x] = sy;
+    }
+}
+
+/* Eq. 30a-b with C_1 of Eq. 31a and C_2 read as (G/2)(1 - kappa^P) (R1). */
+void orc_q_tensor(int nx, int ny, const double *psi, double kappa_p,
+                  double kappa_li, double *Qxx, double *Qyy, double *Qxy) {
+  double C1 = 5.0 / 6.0 * (kappa_p - 1.0);
+  double C2 = 0.5 * G * (1.0 - kappa_p);
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double p0 = psi[y * nx + x];
+      double q[2][2] = {{0, 0}, {0, 0}};
+      for (int i = 1; i < 9; ++i) {
+        double d = psi[wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)] - p0;
+        int c[2] = {CX[i], CY[i]};
+        for (int al = 0; al < 2; ++al)
+          for (int be = 0; be < 2; ++be) {
+            double delta = (al == be) ? 1.0 : 0.0;
+            double C = C1 * G * delta + C2 * (c[al] * c[be] - CS2 * delta) +
+                       kappa_li * 0.5 * G * c[al] * c[be];
+            q[al][be] += omega_sc(i) * C * d;
+          }
+      }
+      Qxx[y * nx + x] = p0 * q[0][0];
+      Qyy[y * nx + x] = p0 * q[1][1];
+      Qxy[y * nx + x] = p0 * q[0][1];
+    }
+}
+
+/* Eq. 24, first line, with the weights w_i (R2). */
+void orc_gradient(int nx, int ny, const double *phi, double *gx, double *gy) {
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double sx = 0.0, sy = 0.0;
+      for (int i = 0; i < 9; ++i) {
+        double v = phi[wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)];
+        sx += WGT[i] * v * CX[i];
+        sy += WGT[i] * v * CY[i];
+      }
+      gx[y * nx + x] = sx / CS2;
+      gy[y * nx + x] = sy / CS2;
+    }
+}
+
+/* Eq. 24, second line. */
+void orc_laplacian(int nx, int ny, const double *phi, double *lap) {
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double c = phi[y * nx + x], s = 0.0;
+      for (int i = 0; i < 9; ++i)
+        s += WGT[i] * (phi[wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)] - c);
+      lap[y * nx + x] = 2.0 * s / CS2;
+    }
+}
+
+/* ---- exported small helpers ---------------------------------------------- */
+double orc_pressure(const orc_params *p, double rho) { return eos_pressure(p, rho); }
+double orc_mu_b(const orc_params *p, double rho) { return eos_mu_b(p, rho); }
+double orc_psi(const orc_params *p, double rho) {
+  unsigned fl = 0;
+  return psi_of_rho(p, rho, &fl);
+}
+void orc_matrices(double *m, double *minv) {
+  memcpy(m, MM, sizeof(MM));
+  memcpy(minv, MINV, sizeof(MINV));
+}
+void orc_feq(int32_t model, double rho, double ux, double uy, double *feq) {
+  if (model == ORC_MODEL_FE)
+    feq_well_balanced(rho, ux, uy, feq);
+  else
+    feq_standard(rho, ux, uy, feq);
+}
+void orc_forcing_fe(double ux, double uy, double Fx, double Fy, double gx,
+                    double gy, double *Fi) {
+  forcing_well_balanced(ux, uy, Fx, Fy, gx, gy, Fi);
+}
+
+/* Population layout: f[i * N + y * nx + x], N = nx * ny, holding f_i(x, t)
+ * after streaming (the left-hand side of Eq. 1 at the previous step). */
+
+/* Initial state: f = f^eq(rho0, u0) (Sec. 5.3 and 5.4 initialise with the
+ * equilibrium; u0 may be NULL for a fluid at rest). */
+void orc_init(const orc_params *p, const double *rho0, const double *ux0,
+              const double *uy0, double *f) {
+  size_t N = (size_t)p->nx * p->ny;
+  for (size_t n = 0; n < N; ++n) {
+    double feq[9];
+    orc_feq(p->model, rho0[n], ux0 ? ux0[n] : 0.0, uy0 ? uy0[n] : 0.0, feq);
+    for (int i = 0; i < 9; ++i) f[i * N + n] = feq[i];
+  }
+}
+
+/* Per-step field work shared by the step and by the field export: density,
+ * and the model's force ingredients.  Arrays are length N. */
+typedef struct {
+  double *rho, *psi, *Sx, *Sy, *Qxx, *Qyy, *Qxy; /* pseudopotential */
+  double *lap, *mu, *gmx, *gmy, *grx, *gry;       /* free energy */
+} orc_work;
+
+static void work_alloc(orc_work *w, size_t N) {
+  double **ptrs[] = {&w->rho, &w->psi, &w->Sx,  &w->Sy,  &w->Qxx, &w->Qyy,
+                     &w->Qxy, &w->lap, &w->mu,  &w->gmx, &w->gmy, &w->grx,
+                     &w->gry};
+  for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k)
+    *ptrs[k] = (double *)calloc(N, sizeof(double));
+}
+
+static void work_free(orc_work *w) {
+  free(w->rho); free(w->psi); free(w->Sx); free(w->Sy); free(w->Qxx);
+  free(w->Qyy); free(w->Qxy); free(w->lap); free(w->mu); free(w->gmx);
+  free(w->gmy); free(w->grx); free(w->gry);
+}
+
+/* Eq. 6a, then the model's field quantities (Sec. 2.1 / Sec. 2.2). */
+static unsigned fields_and_forces(const orc_params *p, const double *f,
+                                  orc_work *w) {
+  int nx = p->nx, ny = p->ny;
+  size_t N = (size_t)nx * ny;
+  unsigned flags = 0;
+#pragma omp parallel for schedule(static) reduction(| : flags)
+  for (size_t n = 0; n < N; ++n) {
+    double s = 0.0;
+    for (int i = 0; i < 9; ++i) s += f[i * N + n];
+    w->rho[n] = s;
+    if (!isfinite(s)) flags |= ORC_FLAG_NONFINITE;
+    if (!eos_domain_ok(p, s)) flags |= ORC_FLAG_EOS_DOMAIN;
+  }
+  if (p->model == ORC_MODEL_P) {
+#pragma omp parallel for schedule(static) reduction(| : flags)
+    for (size_t n = 0; n < N; ++n) w->psi[n] = psi_of_rho(p, w->rho[n], &flags);
+    orc_sc_sum(nx, ny, w->psi, w->Sx, w->Sy);
+    orc_q_tensor(nx, ny, w->psi, p->kappa_p, p->kappa_li, w->Qxx, w->Qyy, w->Qxy);
+  } else {
+    /* mu = mu_b(rho) - kappa lap(rho) (Sec. 2.2), then grad(mu), grad(rho). */
+    orc_laplacian(nx, ny, w->rho, w->lap);
+#pragma omp parallel for schedule(static)
+    for (size_t n = 0; n < N; ++n)
+      w->mu[n] = eos_mu_b(p, w->rho[n]) - p->kappa * w->lap[n];
+    orc_gradient(nx, ny, w->mu, w->gmx, w->gmy);
+    orc_gradient(nx, ny, w->rho, w->grx, w->gry);
+  }
+  return flags;
+}
+
+/* Total force at node n (R6) and, for the pseudopotential, K = |F_int|^2/psi^2
+ * evaluated as G^2 |S|^2 (R3). */
+static void node_force(const orc_params *p, const orc_work *w, size_t n,
+                       double *Fx, double *Fy, double *K) {
+  if (p->model == ORC_MODEL_P) {
+    double fxi = -G * w->psi[n] * w->Sx[n]; /* Eq. 10 */
+    double fyi = -G * w->psi[n] * w->Sy[n];
+    *K = G * G * (w->Sx[n] * w->Sx[n] + w->Sy[n] * w->Sy[n]);
+    *Fx = fxi + p->fx;
+    *Fy = fyi + p->fy;
+  } else {
+    *Fx = -w->rho[n] * w->gmx[n] + p->fx; /* F = -rho grad(mu) */
+    *Fy = -w->rho[n] * w->gmy[n] + p->fy;
+    *K = 0.0;
+  }
+}
+
+/* Export rho and u (Eq. 6a-b) for the current populations. */
+uint32_t orc_fields(const orc_params *p, const double *f, double *rho,
+                    double *ux, double *uy) {
+  size_t N = (size_t)p->nx * p->ny;
+  orc_work w;
+  work_alloc(&w, N);
+  unsigned flags = fields_and_forces(p, f, &w);
+  for (size_t n = 0; n < N; ++n) {
+    double Fx, Fy, K, jx = 0.0, jy = 0.0;
+    node_force(p, &w, n, &Fx, &Fy, &K);
+    for (int i = 0; i < 9; ++i) {
+      jx += f[i * N + n] * CX[i];
+      jy += f[i * N + n] * CY[i];
+    }
+    if (rho) rho[n] = w.rho[n];
+    if (ux) ux[n] = (jx + 0.5 * Fx) / w.rho[n];
+    if (uy) uy[n] = (jy + 0.5 * Fy) / w.rho[n];
+  }
+  work_free(&w);
+  return flags;
+}
+
+/* One collision at node n: Eq. 1 written in moment space,
+ *   m* = m - Lambda (m - m^eq) + (I - Lambda/2) mF + mC,   f* = M^-1 m*. */
+static void collide_node(const orc_params *p, const double *f, size_t N,
+                         const orc_work *w, size_t n, double *fstar) {
+  double fn[9], feq[9], m[9], meq[9], mF[9], mC[9], ms[9];
+  double Fx, Fy, K;
+  double rho = w->rho[n];
+  for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
+  node_force(p, w, n, &Fx, &Fy, &K);
+
+  /* Eq. 6b. */
+  double jx = 0.0, jy = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    jx += fn[i] * CX[i];
+    jy += fn[i] * CY[i];
+  }
+  double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho;
+
+  const double *tau = p->tau;
+  for (int i = 0; i < 9; ++i) mC[i] = 0.0;
+
+  if (p->model == ORC_MODEL_P) {
+    feq_standard(rho, ux, uy, feq); /* Eq. 4 */
+    /* Eq. 32 (forcing moments, consistency term scaled by kappa^P). */
+    double uF = ux * Fx + uy * Fy;
+    double ks = p->kappa_p * p->sigma_li * K;
+    mF[0] = 0.0;
+    mF[1] = 6.0 * uF + 12.0 * ks / (tau[1] - 0.5);
+    mF[2] = -6.0 * uF - 12.0 * ks / (tau[2] - 0.5);
+    mF[3] = Fx;
+    mF[4] = -Fx;
+    mF[5] = Fy;
+    mF[6] = -Fy;
+    mF[7] = 2.0 * (ux * Fx - uy * Fy);
+    mF[8] = ux * Fy + uy * Fx;
+    /* Eq. 13 (source moments) with the Q of Eq. 30. */
+    double qs = w->Qxx[n] + w->Qyy[n];
+    mC[1] = 1.5 * qs / tau[1];
+    mC[2] = -1.5 * qs / tau[2];
+    mC[7] = -(w->Qxx[n] - w->Qyy[n]) / tau[7];
+    mC[8] = -w->Qxy[n] / tau[8];
+  } else {
+    double Fi[9];
+    feq_well_balanced(rho, ux, uy, feq); /* Eq. 20 */
+    forcing_well_balanced(ux, uy, Fx, Fy, w->grx[n], w->gry[n], Fi); /* Eq. 21 */
+    mat_vec(MM, Fi, mF);
+  }
+
+  mat_vec(MM, fn, m);
+  mat_vec(MM, feq, meq);
+  for (int k = 0; k < 9; ++k) {
+    double lam = 1.0 / tau[k];
+    ms[k] = m[k] - lam * (m[k] - meq[k]) + (1.0 - 0.5 * lam) * mF[k] + mC[k];
+  }
+  mat_vec(MINV, ms, fstar);
+}
+
+/* Advance nsteps time steps in place.  Returns the OR of the sticky flags
+ * raised on the way.  Streaming: f_i(x + c_i, t + 1) = f*_i(x, t), periodic. */
+uint32_t orc_step(const orc_params *p, double *f, int64_t nsteps) {
+  int nx = p->nx, ny = p->ny;
+  size_t N = (size_t)nx * ny;
+  double *fnew = (double *)malloc(9 * N * sizeof(double));
+  orc_work w;
+  work_alloc(&w, N);
+  unsigned flags = 0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    flags |= fields_and_forces(p, f, &w);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        size_t n = (size_t)y * nx + x;
+        double fstar[9];
+        collide_node(p, f, N, &w, n, fstar);
+        for (int i = 0; i < 9; ++i) {
+          size_t dst = (size_t)wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx);
+          fnew[i * N + dst] = fstar[i];
+        }
+      }
+    memcpy(f, fnew, 9 * N * sizeof(double));
+  }
+  for (size_t k = 0; k < 9 * N; ++k)
+    if (!isfinite(f[k])) {
+      flags |= ORC_FLAG_NONFINITE;
+      break;
+    }
+  work_free(&w);
+  free(fnew);
+  return flags;
+}
+
+int32_t orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
