@@ -100,7 +100,7 @@ def lib():
         L.orc_mu_b.restype = ctypes.c_double
         L.orc_psi.argtypes = [P, ctypes.c_double]
         L.orc_psi.restype = ctypes.c_double
-        L.orc_matrices.argtypes = [_D, _D]
+        L.orc_matrices.argtypes = [_D, _D, _D]
         L.orc_feq.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, _D]
         L.orc_forcing_fe.argtypes = [ctypes.c_double] * 6 + [_D]
@@ -131,10 +131,12 @@ def num_threads() -> int:
 
 
 def matrices():
+    """(M of Eq. 48, M^-1 as printed in Eq. 49, 36 M^-1 as applied)."""
     m = np.zeros((9, 9))
     mi = np.zeros((9, 9))
-    lib().orc_matrices(_ptr(m), _ptr(mi))
-    return m, mi
+    mi36 = np.zeros((9, 9))
+    lib().orc_matrices(_ptr(m), _ptr(mi), _ptr(mi36))
+    return m, mi, mi36
 
 
 def feq(model: int, rho: float, ux: float, uy: float) -> np.ndarray:

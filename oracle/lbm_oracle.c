@@ -23,7 +23,8 @@
  *   - FP64 everywhere, compiled with -ffp-contract=off (no fused multiply-add);
  *   - equilibria and the free-energy forcing are built in velocity space,
  *     then mapped to moments with explicit 9x9 products by M (Eq. 48);
- *     post-collision populations come back through the printed M^-1 (Eq. 49);
+ *     post-collision populations come back through M^-1 (Eq. 49), applied
+ *     as its integer multiple 36 M^-1 followed by a division by 36;
  *   - every node's quantities are computed from full-field arrays in separate
  *     sweeps (density, then potential / chemical potential, then the
  *     per-node collision), so that a reader can follow the paper by eye.
@@ -78,6 +79,11 @@ static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 static const double WGT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
                               1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+/* The same weights times 36 (16, 4, 1): the equilibria and the forcing
+ * multiply by these integers and divide by 36 at the end, so that the
+ * weights sum to one exactly and f^eq carries exactly the mass rho (a
+ * rounded 1/9 would bias every step's density, against Eq. 7a / 22a). */
+static const double WGT36[9] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
 static const double CS2 = 1.0 / 3.0; /* c_s^2 for c = 1 */
 static const double G = -1.0;        /* interaction sign chosen after Eq. 11 */
 
@@ -107,6 +113,18 @@ static const double MINV[9][9] = {
     {1. / 9, 1. / 18, 1. / 36, -1. / 6, -1. / 12, 1. / 6, 1. / 12, 0, -1. / 4},
     {1. / 9, 1. / 18, 1. / 36, -1. / 6, -1. / 12, -1. / 6, -1. / 12, 0, 1. / 4},
     {1. / 9, 1. / 18, 1. / 36, 1. / 6, 1. / 12, -1. / 6, -1. / 12, 0, -1. / 4}};
+
+/* Eq. 49 times 36: the same rational matrix with integer entries.  The
+ * collision applies it and divides by 36, so that no entry is a rounded
+ * fraction (a rounded 1/9 would make sum_i f*_i = 9 fl(1/9) rho*, a
+ * systematic loss of mass every step, against the exact conservation of
+ * Eq. 7a / 22a). */
+static const double MINV36[9][9] = {
+    {4, -4, 4, 0, 0, 0, 0, 0, 0},       {4, -1, -2, 6, -6, 0, 0, 9, 0},
+    {4, -1, -2, 0, 0, 6, -6, -9, 0},    {4, -1, -2, -6, 6, 0, 0, 9, 0},
+    {4, -1, -2, 0, 0, -6, 6, -9, 0},    {4, 2, 1, 6, 3, 6, 3, 0, 9},
+    {4, 2, 1, -6, -3, 6, 3, 0, -9},     {4, 2, 1, -6, -3, -6, -3, 0, 9},
+    {4, 2, 1, 6, 3, -6, -3, 0, -9}};
 
 static void mat_vec(const double A[9][9], const double *v, double *out) {
   for (int r = 0; r < 9; ++r) {
@@ -167,7 +185,7 @@ static void feq_standard(double rho, double ux, double uy, double *feq) {
     double cu = CX[i] * ux + CY[i] * uy;
     double uu = ux * ux + uy * uy;
     double quad = (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2);
-    feq[i] = WGT[i] * rho * (1.0 + cu / CS2 + quad);
+    feq[i] = WGT36[i] * rho * (1.0 + cu / CS2 + quad) / 36.0;
   }
 }
 
@@ -175,11 +193,11 @@ static void feq_standard(double rho, double ux, double uy, double *feq) {
  * printed in Eq. 20. */
 static void feq_well_balanced(double rho, double ux, double uy, double *feq) {
   double uu = ux * ux + uy * uy;
-  feq[0] = rho - WGT[0] * rho * uu / (2.0 * CS2);
+  feq[0] = rho - WGT36[0] * rho * uu / (2.0 * CS2) / 36.0;
   for (int i = 1; i < 9; ++i) {
     double cu = CX[i] * ux + CY[i] * uy;
     double quad = (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2);
-    feq[i] = WGT[i] * rho * (cu / CS2 + quad);
+    feq[i] = WGT36[i] * rho * (cu / CS2 + quad) / 36.0;
   }
 }
 
@@ -196,8 +214,8 @@ static void forcing_well_balanced(double ux, double uy, double Fx, double Fy,
     double cB = CX[i] * Bx + CY[i] * By;
     double second = cu * cB - CS2 * (ux * Bx + uy * By);
     double c2 = (double)(CX[i] * CX[i] + CY[i] * CY[i]);
-    Fi[i] = WGT[i] * (cF / CS2 + second / (CS2 * CS2) +
-                      0.5 * (c2 / CS2 - 2.0) * ug);
+    Fi[i] = WGT36[i] * (cF / CS2 + second / (CS2 * CS2) +
+                        0.5 * (c2 / CS2 - 2.0) * ug) / 36.0;
   }
 }
 
@@ -287,9 +305,10 @@ double orc_psi(const orc_params *p, double rho) {
   unsigned fl = 0;
   return psi_of_rho(p, rho, &fl);
 }
-void orc_matrices(double *m, double *minv) {
+void orc_matrices(double *m, double *minv, double *minv36) {
   memcpy(m, MM, sizeof(MM));
   memcpy(minv, MINV, sizeof(MINV));
+  memcpy(minv36, MINV36, sizeof(MINV36));
 }
 void orc_feq(int32_t model, double rho, double ux, double uy, double *feq) {
   if (model == ORC_MODEL_FE)
@@ -462,7 +481,8 @@ static void collide_node(const orc_params *p, const double *f, size_t N,
     double lam = 1.0 / tau[k];
     ms[k] = m[k] - lam * (m[k] - meq[k]) + (1.0 - 0.5 * lam) * mF[k] + mC[k];
   }
-  mat_vec(MINV, ms, fstar);
+  mat_vec(MINV36, ms, fstar);
+  for (int i = 0; i < 9; ++i) fstar[i] /= 36.0;
 }
 
 /* Advance nsteps time steps in place.  Returns the OR of the sticky flags

@@ -33,7 +33,7 @@ def test_moment_matrix_rows_are_velocity_polynomials():
     """Eq. 48 rows against the Lallemand-Luo moment definitions built from the
     velocity set: 1, e = 3|c|^2 - 4, zeta = (9|c|^4 - 21|c|^2)/2 + 4, c_x,
     q_x = (3|c|^2 - 5) c_x, c_y, q_y, c_x^2 - c_y^2, c_x c_y."""
-    M, Minv = oracle.matrices()
+    M, Minv, _ = oracle.matrices()
     c2 = CX ** 2 + CY ** 2
     rows = np.array([np.ones(9), 3 * c2 - 4, (9 * c2 ** 2 - 21 * c2) / 2 + 4, CX,
                      (3 * c2 - 5) * CX, CY, (3 * c2 - 5) * CY, CX ** 2 - CY ** 2, CX * CY])
@@ -41,17 +41,21 @@ def test_moment_matrix_rows_are_velocity_polynomials():
 
 
 def test_moment_matrix_inverse():
-    """Eq. 49 is the inverse of Eq. 48."""
-    M, Minv = oracle.matrices()
+    """Eq. 49 is the inverse of Eq. 48; the integer matrix the collision
+    applies is exactly 36 times it (M times it is 36 I in exact integers)."""
+    M, Minv, Minv36 = oracle.matrices()
     assert np.abs(M @ Minv - np.eye(9)).max() < 1e-15
     assert np.abs(Minv @ M - np.eye(9)).max() < 1e-15
+    assert np.array_equal(Minv36, np.round(Minv36))
+    assert np.array_equal(M @ Minv36, 36 * np.eye(9))
+    assert np.abs(Minv36 / 36 - Minv).max() < 1e-16
 
 
 # ---------------------------------------------------------------- T2: equilibria
 @pytest.mark.parametrize("U", [0.0, 0.03, -0.11])
 def test_equilibrium_moments_1d_match_appendix(U):
     """App. E Eq. 66 (P) and App. D Eq. 50 (FE) print the 1-D moments."""
-    M, _ = oracle.matrices()
+    M = oracle.matrices()[0]
     rho = 1.7
     mP = M @ oracle.feq(oracle.MODEL_P, rho, U, 0.0)
     expP = [rho, rho * (-2 + 3 * U * U), rho * (1 - 3 * U * U), rho * U, -rho * U, 0, 0,
@@ -82,7 +86,7 @@ def test_fe_forcing_moments_match_appendix_d():
     """M times the Eq. 21 forcing, 1-D case, against App. D Eq. 50 for the
     e, zeta, j_x, q_x rows; the p_xx row equals 2UF + 2 c_s^2 U d_x rho (the
     printed 4 c_s^2 coefficient does not follow from Eq. 21)."""
-    M, _ = oracle.matrices()
+    M = oracle.matrices()[0]
     U, F, g = 0.021, -3.3e-3, 0.17
     mF = M @ oracle.forcing_fe(U, 0.0, F, 0.0, g, 0.0)
     cs2 = 1 / 3
