@@ -1,0 +1,195 @@
+/*
+ * lbm.h -- C ABI of the MI355X D2Q9 multiphase lattice Boltzmann library.
+ *
+ * The library advances a periodic D2Q9 lattice with one of the two models
+ * compared by Czelusniak et al., "Fundamental comparison between the
+ * pseudopotential and the free energy lattice Boltzmann methods"
+ * (arXiv 2403.11167):
+ *
+ *   LBM_MODEL_P   modified pseudopotential model (Sec. 2.1 and Sec. 4):
+ *                 MRT lattice Boltzmann equation (Eq. 1) with the standard
+ *                 equilibrium (Eq. 4), Shan-Chen force (Eq. 10) on the
+ *                 Yuan-Schaefer potential psi(rho) (Eq. 11, G = -1), the
+ *                 kappa^P-scaled consistency forcing (Eq. 32) and the source
+ *                 term (Eq. 13) built on the width-controlling Q tensor
+ *                 (Eq. 30-31, with C_2 = (G/2)(1 - kappa^P), the reading that
+ *                 App. C Eq. 41b and App. E Eq. 76 require);
+ *   LBM_MODEL_FE  improved well-balanced free-energy model (Sec. 2.2):
+ *                 equilibrium of Eq. 20 and forcing of Eq. 21 with A = 0 and
+ *                 p_g = 0, force F = -rho grad(mu), mu = mu_b(rho) -
+ *                 kappa lap(rho), 9-point stencils of Eq. 24 (with weights).
+ *
+ * Equations of state: Carnahan-Starling (Eq. 28, mu_b from Eq. 29) and van
+ * der Waals (p = rho R T/(1 - b rho) - a rho^2).  Lattice units throughout:
+ * c = dx = dt = 1, c_s^2 = 1/3.
+ *
+ * Memory and streams.  All device memory is owned by the caller: a workspace
+ * of lbm_workspace_bytes() bytes and the initial density field.  The context
+ * returned by lbm_init() is a small host object holding non-owning pointers
+ * into that workspace; it must not outlive it.  Every device operation is
+ * enqueued on the HIP stream given to lbm_init() (NULL = the null stream).
+ * Only lbm_observe() and the lbm_batch_run() / lbm_batch_observe() calls
+ * synchronise that stream.  One context per stream; contexts on different
+ * streams are independent.  The library holds no global state.
+ *
+ * Errors.  Every entry point returns an lbm_status.  Invalid arguments are
+ * detected on the host before any device work is enqueued and leave all
+ * state untouched.  Conditions that arise on the device during a run are
+ * not errors: they raise sticky flags (LBM_FLAG_*) reported by
+ * lbm_observe().
+ *
+ * Layout.  Node (x, y) has linear index n = y * nx + x (x fastest).  Field
+ * arrays (densities, velocities) are nx * ny contiguous doubles in that
+ * order.  Populations are stored structure-of-arrays, one plane of nx * ny
+ * values per velocity, velocities in the order of Eq. 2:
+ * c_0 = (0,0), c_1..c_4 = (1,0),(0,1),(-1,0),(0,-1), c_5..c_8 = (1,1),
+ * (-1,1),(-1,-1),(1,-1).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_INVALID_ARG = -1,  /* bad pointer, size or parameter value        */
+  LBM_ERR_EOS_DOMAIN = -2,   /* equation of state undefined for an input    */
+  LBM_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement */
+  LBM_ERR_WORKSPACE = -4,    /* workspace missing, too small or misaligned  */
+  LBM_ERR_HIP = -5,          /* a HIP runtime call failed                   */
+  LBM_ERR_NO_CONVERGENCE = -6 /* a host-side solver did not converge        */
+} lbm_status;
+
+typedef enum { LBM_MODEL_P = 0, LBM_MODEL_FE = 1 } lbm_model;
+typedef enum { LBM_EOS_VDW = 0, LBM_EOS_CS = 1 } lbm_eos;
+typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_precision;
+
+/* Sticky device flags (lbm_obs.flags). */
+#define LBM_FLAG_NONFINITE 1u  /* a density became NaN or infinite          */
+#define LBM_FLAG_PSI_CLAMP 2u  /* p_EOS > rho c_s^2 somewhere: psi^2 < 0 was
+                                  clamped to 0 (pseudopotential only)        */
+#define LBM_FLAG_EOS_DOMAIN 4u /* a density left the EOS domain (b rho >= 1
+                                  vdW, b rho/4 >= 1 CS, rho <= 0 for FE)     */
+
+/* Problem statement (Sec. 2, Sec. 5).  Plain data; copied by lbm_init(). */
+typedef struct {
+  int32_t nx, ny;       /* periodic lattice, 1 <= nx, ny; nx * ny < 2^31   */
+  int32_t model;        /* lbm_model                                        */
+  int32_t eos;          /* lbm_eos                                          */
+  int32_t precision;    /* lbm_precision                                    */
+  int32_t reserved0;    /* must be 0                                        */
+  double a, b, R, T;    /* EOS constants and absolute temperature (> 0)     */
+  double tau[9];        /* relaxation time of each moment row of M (Eq. 3,
+                           order rho, e, zeta, j_x, q_x, j_y, q_y, p_xx,
+                           p_xy); every tau > 1/2; tau[3] == tau[5],
+                           tau[4] == tau[6], tau[7] == tau[8]               */
+  double sigma_li;      /* P: consistency coefficient sigma^Li (Eq. 32)     */
+  double kappa_li;      /* P: surface-tension coefficient kappa^Li (Eq. 30) */
+  double kappa_p;       /* P: interface-width coefficient kappa^P (Eq. 30-32) */
+  double kappa;         /* FE: gradient coefficient kappa (Sec. 2.2), >= 0  */
+  double A;             /* FE: viscosity-tuning A of Eq. 20; must be 0      */
+  double fx, fy;        /* constant body force added to the model force     */
+  double rho_ref;       /* FP32_SHIFTED: reference density of the storage
+                           shift (<= 0: the smallest initial density)       */
+} lbm_params;
+
+/* Observables of the current state (Eq. 6a-b and Sec. 5.2). */
+typedef struct {
+  int64_t step;         /* time steps taken since lbm_init                   */
+  double mass;          /* sum of rho (FP64, compensated)                    */
+  double max_u;         /* max |u| over the lattice                          */
+  double rho_min, rho_max;
+  double rho_in;        /* rho at the probe node (cx, cy)                    */
+  double rho_out;       /* rho at (cx + nx/2, cy + ny/2), periodic           */
+  double dp;            /* p_EOS(rho_in) - p_EOS(rho_out)                    */
+  double r_equimolar;   /* sqrt((mass - N rho_out)/(pi (rho_in - rho_out)))  */
+  double du_max;        /* max |u - u_prev| since the previous observe
+                           (+inf on the first observe)                       */
+  uint32_t flags;       /* OR of LBM_FLAG_* raised since lbm_init            */
+  uint32_t reserved;
+} lbm_obs;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Human-readable text for a status code (static storage). */
+const char* lbm_status_string(lbm_status s);
+
+/* Size in bytes of the device workspace a problem needs.  Host only. */
+lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* Validate p, carve d_workspace (>= lbm_workspace_bytes, 256-byte aligned,
+ * device memory) and enqueue f_i = f_i^eq(rho0, u = 0) on hip_stream, the
+ * initial state of Sec. 5.3-5.4 (Eq. 4 for P, Eq. 20 for FE).  d_rho0 is a
+ * device array of nx*ny doubles, read by the enqueued work.  Returns
+ * LBM_ERR_EOS_DOMAIN if a density of d_rho0 is outside the EOS domain
+ * (checked on the host from a copy).  On success *out receives a new
+ * context. */
+lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
+                    const double* d_rho0, void* hip_stream, lbm_ctx** out);
+
+/* Enqueue n >= 0 time steps of Eq. 1 (pull streaming, fused with the
+ * model's stencils and the moment-space collision).  Asynchronous. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Compute the observables of the current state and, for each non-NULL
+ * pointer, export rho, u_x, u_y (device arrays of nx*ny doubles).  The
+ * probe (cx, cy) is taken modulo the lattice.  Synchronises the stream. */
+lbm_status lbm_observe(lbm_ctx* ctx, int32_t cx, int32_t cy, lbm_obs* out,
+                       double* d_rho, double* d_ux, double* d_uy);
+
+/* Copy the current post-streaming populations f_i(x, t) into d_f (device,
+ * 9*nx*ny doubles, plane i at offset i*nx*ny) / overwrite the state from
+ * d_f (checkpoint and resume).  Asynchronous. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, double* d_f);
+lbm_status lbm_set_populations(lbm_ctx* ctx, const double* d_f);
+
+/* Free the host context (device memory stays with the caller). */
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* ---- host thermodynamics (no device work) ------------------------------ */
+
+/* Critical point of the EOS: van der Waals in closed form, Carnahan-Starling
+ * from p' = p'' = 0 (Sec. 3).  Outputs may not be NULL. */
+lbm_status lbm_eos_critical(int32_t eos, double a, double b, double R,
+                            double* Tc, double* rho_c, double* p_c);
+
+/* Maxwell equal-area coexistence at temperature T: p(rho_v) = p(rho_l) = p0
+ * and the integral of (p - p0)/rho^2 over [rho_v, rho_l] vanishes (Eq. 27).
+ * LBM_ERR_INVALID_ARG above the critical temperature. */
+lbm_status lbm_maxwell(int32_t eos, double a, double b, double R, double T,
+                       double* rho_l, double* rho_v, double* p0);
+
+/* epsilon and sigma^Li = -epsilon/(16 G) that make the pseudopotential
+ * mechanical-stability integral (Eq. 18) vanish at the Maxwell densities:
+ * Newton iteration on Simpson integrals (App. B, Eq. 13-14).
+ * LBM_ERR_EOS_DOMAIN if psi is not real on [rho_v, rho_l]. */
+lbm_status lbm_sigma_li_theory(int32_t eos, double a, double b, double R,
+                               double T, double* eps, double* sigma_li);
+
+/* Free-energy planar theory (Eq. 26, App. B Eq. 15): max-slope interface
+ * width (rho_l - rho_v)/max|d rho/dx| and surface tension
+ * kappa * integral of (d rho/dx) d rho. */
+lbm_status lbm_fe_planar_theory(int32_t eos, double a, double b, double R,
+                                double T, double kappa, double* width,
+                                double* gamma);
+
+/* Parameters that match the pseudopotential model to a free-energy
+ * interface (Sec. 3-4, App. B-C): sigma^Li from App. B; kappa^P such that
+ * the max-slope width of App. C Eq. 44 equals target_width (<= 0: the FE
+ * width for kappa_fe); kappa^Li such that the surface tension of Eq. 46
+ * equals the FE one for kappa_fe (Eq. 26). */
+lbm_status lbm_match_p_to_fe(int32_t eos, double a, double b, double R,
+                             double T, double kappa_fe, double target_width,
+                             double* sigma_li, double* kappa_p,
+                             double* kappa_li);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,1252 @@
+// lbm_kernels.hip -- gfx950 kernels and C ABI of the D2Q9 multiphase lattice
+// Boltzmann library (pseudopotential and well-balanced free-energy models of
+// Czelusniak et al., arXiv 2403.11167).  See include/lbm.h for the contract.
+//
+// Data layout in HBM
+//   Populations: structure of arrays, plane i (Eq. 2 order) of nx*ny values,
+//   x fastest.  What is stored is the post-collision, pre-streaming field
+//   g*_i(x) = f*_i(x) - s_i, where s_i = f_i^eq(rho_ref, u = 0) of the model
+//   (w_i rho_ref for the pseudopotential, rho_ref delta_i0 for the free
+//   energy) and rho_ref = 0 for FP64 storage.  A step pulls
+//   f_i(x) = s_i + g*_i(x - c_i) (streaming of Eq. 1), so reads are shifted
+//   by at most one node and writes are aligned and coalesced.
+//
+// One step = one launch of a fused kernel.  A workgroup of BX threads owns a
+// strip of BX columns and a segment of LY rows and sweeps it row by row:
+//   1. pull row y+H (H = 1 for P, 2 for FE) into registers, form rho
+//      (Eq. 6a) and the row of psi (Eq. 11) or rho into an LDS ring that
+//      also holds H halo columns on each side;
+//   2. FE only: form mu = mu_b - kappa lap(rho) (Sec. 2.2, Eq. 24) for row
+//      y+1 into a second LDS ring;
+//   3. collide row y in moment space with the model's force / source terms
+//      read from the 3x3 LDS stencil, and store it.
+// Halo rows at the segment ends and the H halo columns are recomputed from
+// the populations.  No MFMA: the update is a bandwidth-bound stencil.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "lbm.h"
+
+namespace lbmk {
+
+enum { EOS_VDW = 0, EOS_CS = 1 };
+enum { MODEL_P = 0, MODEL_FE = 1 };
+
+// Kernel-argument parameter block in the compute type C.
+template <class C>
+struct KParams {
+  int nx, ny;
+  int nstrips, nseg, LY;
+  int xcd_remap;  // 1: map workgroups so that each XCD gets a contiguous
+                  // band of tiles (neighbouring tiles share its L2)
+  C a, b, RT;
+  C lam_e, lam_z, lam_q, lam_nu;  // 1/tau of the e, zeta, q, p rows (Eq. 3)
+  C hl_e, hl_z, hl_q, hl_nu;      // 1 - lam/2 (Eq. 1 forcing factor)
+  C sig_e, sig_z;  // P: 12 kappa^P sigma^Li/(tau - 1/2), multiplies G^2|S|^2
+  C qa, qb;        // P: Q tensor coefficients, see q_terms()
+  C kappa;         // FE
+  C fx, fy;        // constant body force
+  C rho_ref;       // sum of the storage shift s_i
+  C s0, sax, sdg;  // storage shift for i = 0, axis and diagonal velocities
+  // Reference terms for chemical-potential differences (shifted storage):
+  C inv_rho_ref;   // 1 / rho_ref
+  C om_ref;        // 1 - b rho_ref (vdW) or 1 - b rho_ref / 4 (CS)
+};
+
+template <class C>
+__device__ __forceinline__ C d_sqrt(C v) {
+  if constexpr (sizeof(C) == 4) return sqrtf(v); else return sqrt(v);
+}
+template <class C>
+__device__ __forceinline__ C d_log(C v) {
+  if constexpr (sizeof(C) == 4) return logf(v); else return log(v);
+}
+
+// ---- equations of state ---------------------------------------------------
+// Carnahan-Starling (Eq. 28) and van der Waals pressure.
+template <int EOS, class C>
+__device__ __forceinline__ C eos_p(C rho, const KParams<C>& kp) {
+  if constexpr (EOS == EOS_CS) {
+    C e = kp.b * rho * C(0.25);
+    C om = C(1) - e;
+    C num = C(1) + e * (C(1) + e * (C(1) - e));
+    return rho * kp.RT * num / (om * om * om) - kp.a * rho * rho;
+  } else {
+    return rho * kp.RT / (C(1) - kp.b * rho) - kp.a * rho * rho;
+  }
+}
+
+// Bulk chemical potential: Eq. 29 (CS); for vdW the antiderivative of
+// (1/rho) dp/drho, RT ln(rho/(1 - b rho)) + RT b rho/(1 - b rho) - 2 a rho.
+template <int EOS, class C>
+__device__ __forceinline__ C eos_mu(C rho, const KParams<C>& kp) {
+  if constexpr (EOS == EOS_CS) {
+    C e = kp.b * rho * C(0.25);
+    C om = C(1) - e;
+    return kp.RT * (C(3) - e) / (om * om * om) + kp.RT * d_log(rho) + kp.RT -
+           C(2) * kp.a * rho;
+  } else {
+    C inv = C(1) / (C(1) - kp.b * rho);
+    return kp.RT * d_log(rho * inv) + kp.RT * kp.b * rho * inv -
+           C(2) * kp.a * rho;
+  }
+}
+
+template <class C>
+__device__ __forceinline__ C d_log1p(C v) {
+  if constexpr (sizeof(C) == 4) return log1pf(v); else return log1p(v);
+}
+
+// Chemical potential up to a constant, from the density deviation
+// d = rho - rho_ref.  FP64 storage (rho_ref = 0): mu_b(d) itself.  Shifted
+// storage: mu_b(rho_ref + d) - mu_b(rho_ref) written so that every term is
+// O(d) with full relative precision (log1p for the logarithms; factored
+// differences of the rational terms), because only differences of mu enter
+// the force and an O(1) float mu_b would put 2^-24 noise on them.
+//   vdW: RT ln(1 + d/rho_r) - RT ln(1 - b d/(1 - b rho_r))
+//        + RT b d / ((1 - b rho)(1 - b rho_r)) - 2 a d
+//   CS, u = 1 - b rho/4: RT [g(u) - g(u_r)] + RT ln(1 + d/rho_r) - 2 a d with
+//        g = (2 + u)/u^3 and g(u) - g(u_r) = (b d/4) [2 (u_r^2 + u u_r + u^2)/
+//        (u^3 u_r^3) + (u + u_r)/(u^2 u_r^2)]
+template <int EOS, class C>
+__device__ __forceinline__ C mu_dev(C d, const KParams<C>& kp) {
+  if constexpr (sizeof(C) == 8) {
+    return eos_mu<EOS>(kp.rho_ref + d, kp);
+  } else {
+    C lr = kp.RT * d_log1p(d * kp.inv_rho_ref);
+    if constexpr (EOS == EOS_CS) {
+      C u = kp.om_ref - kp.b * d * C(0.25), ur = kp.om_ref;
+      C u2 = u * u, ur2 = ur * ur;
+      C dg = kp.b * d * C(0.25) *
+             (C(2) * (ur2 + u * ur + u2) / (u2 * u * ur2 * ur) + (u + ur) / (u2 * ur2));
+      return kp.RT * dg + lr - C(2) * kp.a * d;
+    } else {
+      C om = kp.om_ref - kp.b * d;  // 1 - b rho
+      return lr - kp.RT * d_log1p(-kp.b * d / kp.om_ref) +
+             kp.RT * kp.b * d / (om * kp.om_ref) - C(2) * kp.a * d;
+    }
+  }
+}
+
+template <int MODEL, int EOS, class C>
+__device__ __forceinline__ unsigned domain_flags(C rho, const KParams<C>& kp) {
+  unsigned fl = 0;
+  if (!__builtin_isfinite(rho)) fl |= LBM_FLAG_NONFINITE;
+  C lim = (EOS == EOS_CS) ? kp.b * rho * C(0.25) : kp.b * rho;
+  if (!(lim < C(1))) fl |= LBM_FLAG_EOS_DOMAIN;
+  if (MODEL == MODEL_FE && !(rho > C(0))) fl |= LBM_FLAG_EOS_DOMAIN;
+  return fl;
+}
+
+// Yuan-Schaefer potential, Eq. 11 with G = -1: psi^2 = 2 (rho c_s^2 - p).
+// A negative psi^2 is clamped to zero and flagged.
+template <int EOS, class C>
+__device__ __forceinline__ C psi_of(C rho, const KParams<C>& kp, unsigned& fl) {
+  C arg = C(2) * (rho * C(1.0 / 3.0) - eos_p<EOS>(rho, kp));
+  if (arg < C(0)) {
+    fl |= LBM_FLAG_PSI_CLAMP;
+    arg = C(0);
+  }
+  return d_sqrt(arg);
+}
+
+// ---- streaming ------------------------------------------------------------
+// Pulled deviations g_i(x, y) = g*_i(x - c_i) for one node; rm / r0 / rp are
+// the row offsets of y-1, y, y+1 and xm / x / xp the columns x-1, x, x+1
+// (periodic wrap already applied).
+template <class S, class C>
+__device__ __forceinline__ void pull9(const S* __restrict__ src, size_t N,
+                                      int rm, int r0, int rp, int xm, int x,
+                                      int xp, C g[9]) {
+  g[0] = (C)src[r0 + x];
+  g[1] = (C)src[N + r0 + xm];
+  g[2] = (C)src[2 * N + rm + x];
+  g[3] = (C)src[3 * N + r0 + xp];
+  g[4] = (C)src[4 * N + rp + x];
+  g[5] = (C)src[5 * N + rm + xm];
+  g[6] = (C)src[6 * N + rm + xp];
+  g[7] = (C)src[7 * N + rp + xp];
+  g[8] = (C)src[8 * N + rp + xm];
+}
+
+template <class C>
+__device__ __forceinline__ C sum9(const C g[9]) {
+  return ((g[0] + (g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8])));
+}
+
+// ---- the 3x3 stencils -----------------------------------------------------
+// Neighbour values of a field around the node, indices in Eq. 2 order:
+// v[1..4] = E, N, W, S; v[5..8] = NE, NW, SW, SE; v[0] = centre.
+// Shan-Chen sum S = sum_i omega_i v(x + c_i) c_i (Eq. 10).  Since
+// omega_i = 3 w_i = w_i / c_s^2 this is also the 9-point gradient of Eq. 24.
+template <class C>
+__device__ __forceinline__ void grad_sum(const C v[9], C& sx, C& sy) {
+  sx = (v[1] - v[3]) * C(1.0 / 3.0) + ((v[5] - v[7]) - (v[6] - v[8])) * C(1.0 / 12.0);
+  sy = (v[2] - v[4]) * C(1.0 / 3.0) + ((v[5] - v[7]) + (v[6] - v[8])) * C(1.0 / 12.0);
+}
+
+// Q tensor of Eq. 30: with C_i_ab = alpha delta_ab + beta c_ia c_ib,
+// alpha = C_1 G - C_2 c_s^2 and beta = C_2 + kappa^Li G/2 (qa, qb), returns
+// Qxx + Qyy, Qxx - Qyy and Qxy.
+// Neighbour differences v_i - v_0 are formed first: for a smooth field they
+// are exact (Sterbenz), so the stencil sums keep full relative precision
+// instead of losing it to the cancellation of four O(v) terms.
+template <class C>
+__device__ __forceinline__ void diff_sums(const C v[9], C& ax, C& dg) {
+  C p = v[0];
+  ax = ((v[1] - p) + (v[2] - p)) + ((v[3] - p) + (v[4] - p));
+  dg = ((v[5] - p) + (v[6] - p)) + ((v[7] - p) + (v[8] - p));
+}
+
+template <class C>
+__device__ __forceinline__ void q_terms(const C v[9], C qa, C qb, C& qs, C& qd,
+                                        C& qxy) {
+  C p = v[0];
+  C ax, dg;
+  diff_sums(v, ax, dg);
+  C sw = ax * C(1.0 / 3.0) + dg * C(1.0 / 12.0);  // sum omega_i (v_i - v)
+  C sc = ax * C(1.0 / 3.0) + dg * C(1.0 / 6.0);   // sum omega_i |c_i|^2 (v_i - v)
+  qs = p * (C(2) * qa * sw + qb * sc);
+  qd = p * qb * (((v[1] - v[2]) + (v[3] - v[4])) * C(1.0 / 3.0));
+  qxy = p * qb * (((v[5] - v[6]) + (v[7] - v[8])) * C(1.0 / 12.0));
+}
+
+// 9-point Laplacian of Eq. 24: (2/c_s^2) sum_i w_i (v_i - v).
+template <class C>
+__device__ __forceinline__ C lap9(const C v[9]) {
+  C ax, dg;
+  diff_sums(v, ax, dg);
+  return ax * C(2.0 / 3.0) + dg * C(1.0 / 6.0);
+}
+
+// Gather the 3x3 neighbourhood of LDS column j from three LDS rows.
+template <class C>
+__device__ __forceinline__ void gather(const C* bot, const C* mid, const C* top,
+                                       int j, C v[9]) {
+  v[0] = mid[j];
+  v[1] = mid[j + 1];
+  v[2] = top[j];
+  v[3] = mid[j - 1];
+  v[4] = bot[j];
+  v[5] = top[j + 1];
+  v[6] = top[j - 1];
+  v[7] = bot[j - 1];
+  v[8] = bot[j + 1];
+}
+
+// ---- collision in moment space --------------------------------------------
+// Eq. 1 written for the deviations g = f - s (s an equilibrium at rest, so
+// M s only has rho, e and zeta components):
+//   m* = m - Lambda (m - m^eq) + (I - Lambda/2) mF + mC,  g* = M^-1 m*,
+// with M the moment matrix of Eq. 48, M^-1 of Eq. 49 applied in factored
+// form, m^eq of Eq. 4 (P) or Eq. 20 (FE), mF of Eq. 32 (P) or the moments of
+// Eq. 21 (FE), mC of Eq. 13 (P).  The j rows reduce exactly to j + F.
+template <int MODEL, class C>
+__device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
+                                        C t0, C t1, C t2, C t3,
+                                        const KParams<C>& kp) {
+  // P: t0 = G^2 |S|^2, t1 = Qxx + Qyy, t2 = Qxx - Qyy, t3 = Qxy.
+  // FE: t0 = d_x rho, t1 = d_y rho.
+  C jx = (g[1] - g[3]) + ((g[5] - g[7]) - (g[6] - g[8]));
+  C jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
+  C inv = C(1) / rho;
+  C ux = (jx + C(0.5) * Fx) * inv;  // Eq. 6b
+  C uy = (jy + C(0.5) * Fy) * inv;
+
+  C axs = (g[1] + g[2]) + (g[3] + g[4]);
+  C dgs = (g[5] + g[6]) + (g[7] + g[8]);
+  C me = C(-4) * g[0] - axs + C(2) * dgs;
+  C mz = C(4) * g[0] - C(2) * axs + dgs;
+  C dx1 = g[1] - g[3], dy1 = g[2] - g[4];
+  C d57 = g[5] - g[7], d68 = g[6] - g[8];
+  C mqx = C(-2) * dx1 + (d57 - d68);
+  C mqy = C(-2) * dy1 + (d57 + d68);
+  C mpxx = (g[1] + g[3]) - (g[2] + g[4]);
+  C mpxy = (g[5] + g[7]) - (g[6] + g[8]);
+
+  C ru2 = rho * (ux * ux + uy * uy);
+  C eqe, eqz;
+  if constexpr (MODEL == MODEL_P) {
+    eqe = C(-2) * drho + C(3) * ru2;
+    eqz = drho - C(3) * ru2;
+  } else {
+    eqe = C(-4) * drho + C(3) * ru2;
+    eqz = C(4) * drho - C(3) * ru2;
+  }
+  C eqqx = -rho * ux, eqqy = -rho * uy;
+  C eqpxx = rho * (ux * ux - uy * uy);
+  C eqpxy = rho * ux * uy;
+
+  C uF = ux * Fx + uy * Fy;
+  C Fe, Fz, Fpxx, Fpxy;
+  C Ce = C(0), Cz = C(0), Cpxx = C(0), Cpxy = C(0);
+  if constexpr (MODEL == MODEL_P) {
+    Fe = C(6) * uF + kp.sig_e * t0;
+    Fz = C(-6) * uF - kp.sig_z * t0;
+    Fpxx = C(2) * (ux * Fx - uy * Fy);
+    Fpxy = ux * Fy + uy * Fx;
+    Ce = C(1.5) * t1 * kp.lam_e;
+    Cz = C(-1.5) * t1 * kp.lam_z;
+    Cpxx = -t2 * kp.lam_nu;
+    Cpxy = -t3 * kp.lam_nu;
+  } else {
+    C ug = ux * t0 + uy * t1;
+    Fe = C(6) * uF + C(4) * ug;
+    Fz = -Fe;
+    Fpxx = C(2) * (ux * Fx - uy * Fy) + C(2.0 / 3.0) * (ux * t0 - uy * t1);
+    Fpxy = ux * Fy + uy * Fx + C(1.0 / 3.0) * (ux * t1 + uy * t0);
+  }
+
+  C se = me - kp.lam_e * (me - eqe) + kp.hl_e * Fe + Ce;
+  C sz = mz - kp.lam_z * (mz - eqz) + kp.hl_z * Fz + Cz;
+  C sjx = jx + Fx;
+  C sjy = jy + Fy;
+  C sqx = mqx - kp.lam_q * (mqx - eqqx) - kp.hl_q * Fx;
+  C sqy = mqy - kp.lam_q * (mqy - eqqy) - kp.hl_q * Fy;
+  C spxx = mpxx - kp.lam_nu * (mpxx - eqpxx) + kp.hl_nu * Fpxx + Cpxx;
+  C spxy = mpxy - kp.lam_nu * (mpxy - eqpxy) + kp.hl_nu * Fpxy + Cpxy;
+
+  // M^-1 (Eq. 49) in factored form.  The rest population is closed on the
+  // mass, g*_0 = rho* - sum_{i>0} g*_i (row 0 of M is all ones), which is
+  // the same number without the bias a rounded 1/9 would put on the mass.
+  C r9 = drho * C(1.0 / 9.0);
+  C Aax = r9 - se * C(1.0 / 36.0) - sz * C(1.0 / 18.0);
+  C Adg = r9 + se * C(1.0 / 18.0) + sz * C(1.0 / 36.0);
+  C X1 = (sjx - sqx) * C(1.0 / 6.0);
+  C Y1 = (sjy - sqy) * C(1.0 / 6.0);
+  C P4 = spxx * C(0.25);
+  C X5 = sjx * C(1.0 / 6.0) + sqx * C(1.0 / 12.0);
+  C Y5 = sjy * C(1.0 / 6.0) + sqy * C(1.0 / 12.0);
+  C Q4 = spxy * C(0.25);
+  g[1] = Aax + X1 + P4;
+  g[2] = Aax + Y1 - P4;
+  g[3] = Aax - X1 + P4;
+  g[4] = Aax - Y1 - P4;
+  g[5] = Adg + X5 + Y5 + Q4;
+  g[6] = Adg - X5 + Y5 - Q4;
+  g[7] = Adg - X5 - Y5 + Q4;
+  g[8] = Adg + X5 - Y5 - Q4;
+  g[0] = drho - (((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8])));
+}
+
+// ---- tile mapping -----------------------------------------------------------
+__device__ __forceinline__ int tile_index(int xcd_remap) {
+  int b = blockIdx.x;
+  if (!xcd_remap) return b;
+  // Workgroups are dispatched round-robin over the 8 XCDs; give XCD k the
+  // contiguous band [k*nb/8, (k+1)*nb/8) of tiles so that a tile's
+  // neighbours (and their shared halo lines) usually sit in the same L2.
+  int nb = gridDim.x;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// ---- pseudopotential step ---------------------------------------------------
+template <int EOS, class S, class C, int BX>
+__global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
+                                               S* __restrict__ dst,
+                                               const KParams<C> kp,
+                                               unsigned* __restrict__ flags) {
+  __shared__ C psi_s[4][BX + 2];
+  const int nx = kp.nx, ny = kp.ny;
+  const size_t N = (size_t)nx * ny;
+  const int tile = tile_index(kp.xcd_remap);
+  const int strip = tile % kp.nstrips, seg = tile / kp.nstrips;
+  const int x0 = strip * BX;
+  const int w = min(BX, nx - x0);
+  const int y0 = seg * kp.LY;
+  const int ly = min(kp.LY, ny - y0);
+  const int t = threadIdx.x;
+  const bool active = t < w;
+  const int x = x0 + (active ? t : 0);
+  const int xm = (x == 0) ? nx - 1 : x - 1;
+  const int xp = (x == nx - 1) ? 0 : x + 1;
+  // halo column handled by lanes 0 (left) and 1 (right)
+  const bool hl = t < 2;
+  const int hx = (t == 0) ? wrapi(x0 - 1, nx) : wrapi(x0 + w, nx);
+  const int hxm = (hx == 0) ? nx - 1 : hx - 1;
+  const int hxp = (hx == nx - 1) ? 0 : hx + 1;
+  const int hj = (t == 0) ? 0 : w + 1;
+
+  unsigned fl = 0;
+  C gc[9], gn[9];
+  C drho_c = C(0), drho_n = C(0);
+
+  auto rowoff = [&](int y) { return wrapi(y, ny) * nx; };
+
+  // Rows y0-1 (psi only) and y0 (psi and populations).
+  for (int r = 0; r < 2; ++r) {
+    const int y = y0 - 1 + r;
+    const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
+    if (active) {
+      C g[9];
+      pull9(src, N, rm, r0, rp, xm, x, xp, g);
+      C dr = sum9(g);
+      C rho = kp.rho_ref + dr;
+      fl |= domain_flags<MODEL_P, EOS>(rho, kp);
+      psi_s[r][t + 1] = psi_of<EOS>(rho, kp, fl);
+      if (r == 1) {
+        for (int i = 0; i < 9; ++i) gc[i] = g[i];
+        drho_c = dr;
+      }
+    }
+    if (hl) {
+      C g[9];
+      pull9(src, N, rm, r0, rp, hxm, hx, hxp, g);
+      C rho = kp.rho_ref + sum9(g);
+      psi_s[r][hj] = psi_of<EOS>(rho, kp, fl);
+    }
+  }
+
+  for (int k = 0; k < ly; ++k) {
+    const int y = y0 + k;
+    // pull row y+1 into the ring
+    {
+      const int yn = y + 1;
+      const int r0 = rowoff(yn), rm = rowoff(yn - 1), rp = rowoff(yn + 1);
+      C* row = psi_s[(k + 2) & 3];
+      if (active) {
+        pull9(src, N, rm, r0, rp, xm, x, xp, gn);
+        drho_n = sum9(gn);
+        C rho = kp.rho_ref + drho_n;
+        fl |= domain_flags<MODEL_P, EOS>(rho, kp);
+        row[t + 1] = psi_of<EOS>(rho, kp, fl);
+      }
+      if (hl) {
+        C g[9];
+        pull9(src, N, rm, r0, rp, hxm, hx, hxp, g);
+        C rho = kp.rho_ref + sum9(g);
+        row[hj] = psi_of<EOS>(rho, kp, fl);
+      }
+    }
+    __syncthreads();
+    if (active) {
+      C v[9];
+      gather(psi_s[k & 3], psi_s[(k + 1) & 3], psi_s[(k + 2) & 3], t + 1, v);
+      C sx, sy;
+      grad_sum(v, sx, sy);
+      // Eq. 10 with G = -1: F = psi S; |F_int|^2/psi^2 = G^2 |S|^2.
+      C Fx = v[0] * sx + kp.fx;
+      C Fy = v[0] * sy + kp.fy;
+      C K = sx * sx + sy * sy;
+      C qs, qd, qxy;
+      q_terms(v, kp.qa, kp.qb, qs, qd, qxy);
+      C rho = kp.rho_ref + drho_c;
+      collide<MODEL_P>(gc, drho_c, rho, Fx, Fy, K, qs, qd, qxy, kp);
+      const int off = wrapi(y, ny) * nx + x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) dst[i * N + off] = (S)gc[i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) gc[i] = gn[i];
+      drho_c = drho_n;
+    }
+  }
+  if (fl) atomicOr(flags, fl);
+}
+
+// ---- free-energy step -------------------------------------------------------
+template <int EOS, class S, class C, int BX>
+__global__ __launch_bounds__(BX) void k_step_fe(const S* __restrict__ src,
+                                                S* __restrict__ dst,
+                                                const KParams<C> kp,
+                                                unsigned* __restrict__ flags) {
+  __shared__ C rho_s[8][BX + 4];
+  __shared__ C mu_s[4][BX + 2];
+  const int nx = kp.nx, ny = kp.ny;
+  const size_t N = (size_t)nx * ny;
+  const int tile = tile_index(kp.xcd_remap);
+  const int strip = tile % kp.nstrips, seg = tile / kp.nstrips;
+  const int x0 = strip * BX;
+  const int w = min(BX, nx - x0);
+  const int y0 = seg * kp.LY;
+  const int ly = min(kp.LY, ny - y0);
+  const int t = threadIdx.x;
+  const bool active = t < w;
+  const int x = x0 + (active ? t : 0);
+  const int xm = (x == 0) ? nx - 1 : x - 1;
+  const int xp = (x == nx - 1) ? 0 : x + 1;
+  // rho halo columns x0-2, x0-1, x0+w, x0+w+1 on lanes 0..3
+  const bool hr = t < 4;
+  const int hoff = (t < 2) ? (t - 2) : (w + t - 2);
+  const int hx = wrapi(x0 + hoff, nx);
+  const int hxm = (hx == 0) ? nx - 1 : hx - 1;
+  const int hxp = (hx == nx - 1) ? 0 : hx + 1;
+  const int hj = hoff + 2;  // LDS index of the halo column in rho_s
+  // mu halo columns x0-1 (lane 0) and x0+w (lane 1)
+  const bool hm = t < 2;
+  const int hmj = (t == 0) ? 0 : w + 1;  // index in mu_s
+
+  unsigned fl = 0;
+  C g0[9], g1[9], g2[9];
+  C d0 = C(0), d1 = C(0), d2 = C(0);
+
+  auto rowoff = [&](int y) { return wrapi(y, ny) * nx; };
+
+  // density of row y into ring slot r (and the populations of interior lanes)
+  auto load_row = [&](int y, int slot, C g[9], C& dr) {
+    const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
+    C* row = rho_s[slot & 7];
+    if (active) {
+      pull9(src, N, rm, r0, rp, xm, x, xp, g);
+      dr = sum9(g);
+      fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dr, kp);
+      row[t + 2] = dr;
+    }
+    if (hr) {
+      C h[9];
+      pull9(src, N, rm, r0, rp, hxm, hx, hxp, h);
+      row[hj] = sum9(h);
+    }
+  };
+  // mu of the row in rho slot rs into mu slot ms (needs rho slots rs-1..rs+1)
+  auto mu_row = [&](int rs, int ms) {
+    const C* bot = rho_s[(rs - 1) & 7];
+    const C* mid = rho_s[rs & 7];
+    const C* top = rho_s[(rs + 1) & 7];
+    C* out = mu_s[ms & 3];
+    if (active) {
+      C v[9];
+      gather(bot, mid, top, t + 2, v);
+      out[t + 1] = mu_dev<EOS>(v[0], kp) - kp.kappa * lap9(v);
+    }
+    if (hm) {
+      C v[9];
+      gather(bot, mid, top, hmj + 1, v);
+      out[hmj] = mu_dev<EOS>(v[0], kp) - kp.kappa * lap9(v);
+    }
+  };
+
+  // rho_s holds density deviations rho - rho_ref (rho itself for FP64).
+  // rho slots: row y0-2+r -> slot r.  mu slots: row y0-1+q -> slot q.
+  {
+    C tmp[9];
+    C dtmp;
+    load_row(y0 - 2, 0, tmp, dtmp);
+    load_row(y0 - 1, 1, tmp, dtmp);
+    load_row(y0, 2, g0, d0);
+    load_row(y0 + 1, 3, g1, d1);
+  }
+  __syncthreads();
+  mu_row(1, 0);  // row y0-1
+  mu_row(2, 1);  // row y0
+
+  for (int k = 0; k < ly; ++k) {
+    const int y = y0 + k;
+    load_row(y + 2, k + 4, g2, d2);
+    __syncthreads();
+    mu_row(k + 3, k + 2);  // row y+1
+    __syncthreads();
+    if (active) {
+      C v[9], m[9];
+      gather(rho_s[(k + 1) & 7], rho_s[(k + 2) & 7], rho_s[(k + 3) & 7], t + 2, v);
+      gather(mu_s[k & 3], mu_s[(k + 1) & 3], mu_s[(k + 2) & 3], t + 1, m);
+      C grx, gry, gmx, gmy;
+      grad_sum(v, grx, gry);  // Eq. 24 gradient of rho
+      grad_sum(m, gmx, gmy);  // Eq. 24 gradient of mu
+      C rho = kp.rho_ref + d0;
+      C Fx = -rho * gmx + kp.fx;  // F = -rho grad(mu)
+      C Fy = -rho * gmy + kp.fy;
+      collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp);
+      const int off = wrapi(y, ny) * nx + x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) dst[i * N + off] = (S)g0[i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) { g0[i] = g1[i]; g1[i] = g2[i]; }
+      d0 = d1;
+      d1 = d2;
+    }
+  }
+  if (fl) atomicOr(flags, fl);
+}
+
+// ---- initial state ------------------------------------------------------------
+// Stored g*_i(x) = f^eq_i(rho0(x + c_i), 0) - s_i, so that the first pull
+// yields f_i(x) = f^eq_i(rho0(x), 0) (Eq. 4: w_i rho; Eq. 20: rho delta_i0).
+template <int MODEL, class S>
+__global__ void k_init(const double* __restrict__ rho0, S* __restrict__ dst,
+                       int nx, int ny, double s0, double sax, double sdg) {
+  const size_t N = (size_t)nx * ny;
+  const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const double wt[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x = (int)(n % nx), y = (int)(n / nx);
+    for (int i = 0; i < 9; ++i) {
+      int xs = wrapi(x + cx[i], nx), ys = wrapi(y + cy[i], ny);
+      double r = rho0[(size_t)ys * nx + xs];
+      double feq = (MODEL == MODEL_P) ? wt[i] * r : ((i == 0) ? r : 0.0);
+      double s = (i == 0) ? s0 : (i < 5 ? sax : sdg);
+      dst[i * N + n] = (S)(feq - s);
+    }
+  }
+}
+
+// ---- population import / export (post-streaming f_i(x, t)) ----------------
+template <class S>
+__global__ void k_get_pop(const S* __restrict__ src, double* __restrict__ f,
+                          int nx, int ny, double s0, double sax, double sdg) {
+  const size_t N = (size_t)nx * ny;
+  const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x = (int)(n % nx), y = (int)(n / nx);
+    for (int i = 0; i < 9; ++i) {
+      int xs = wrapi(x - cx[i], nx), ys = wrapi(y - cy[i], ny);
+      double s = (i == 0) ? s0 : (i < 5 ? sax : sdg);
+      f[i * N + n] = s + (double)src[i * N + (size_t)ys * nx + xs];
+    }
+  }
+}
+
+template <class S>
+__global__ void k_set_pop(const double* __restrict__ f, S* __restrict__ dst,
+                          int nx, int ny, double s0, double sax, double sdg) {
+  const size_t N = (size_t)nx * ny;
+  const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x = (int)(n % nx), y = (int)(n / nx);
+    for (int i = 0; i < 9; ++i) {
+      int xs = wrapi(x + cx[i], nx), ys = wrapi(y + cy[i], ny);
+      double s = (i == 0) ? s0 : (i < 5 ? sax : sdg);
+      dst[i * N + n] = (S)(f[i * N + (size_t)ys * nx + xs] - s);
+    }
+  }
+}
+
+// ---- observation (FP64) -------------------------------------------------------
+// Pass 1: rho (Eq. 6a) and, for P, psi (Eq. 11) on every node.
+template <int MODEL, int EOS, class S>
+__global__ void k_obs_rho(const S* __restrict__ src, const KParams<double> kp,
+                          double* __restrict__ rho_w, double* __restrict__ aux_w,
+                          unsigned* __restrict__ flags) {
+  const int nx = kp.nx, ny = kp.ny;
+  const size_t N = (size_t)nx * ny;
+  unsigned fl = 0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x = (int)(n % nx), y = (int)(n / nx);
+    int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    int r0 = y * nx, rm = wrapi(y - 1, ny) * nx, rp = wrapi(y + 1, ny) * nx;
+    double g[9];
+    pull9(src, N, rm, r0, rp, xm, x, xp, g);
+    double rho = kp.rho_ref + sum9(g);
+    fl |= domain_flags<MODEL, EOS>(rho, kp);
+    rho_w[n] = rho;
+    if (MODEL == MODEL_P) aux_w[n] = psi_of<EOS>(rho, kp, fl);
+  }
+  if (fl) atomicOr(flags, fl);
+}
+
+template <class C>
+__device__ __forceinline__ void gather_global(const C* __restrict__ a, int nx,
+                                              int ny, int x, int y, C v[9]) {
+  int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+  int r0 = y * nx, rm = wrapi(y - 1, ny) * nx, rp = wrapi(y + 1, ny) * nx;
+  v[0] = a[r0 + x];
+  v[1] = a[r0 + xp];
+  v[2] = a[rp + x];
+  v[3] = a[r0 + xm];
+  v[4] = a[rm + x];
+  v[5] = a[rp + xp];
+  v[6] = a[rp + xm];
+  v[7] = a[rm + xm];
+  v[8] = a[rm + xp];
+}
+
+// Pass 2 (FE): mu = mu_b(rho) - kappa lap(rho).
+template <int EOS>
+__global__ void k_obs_mu(const KParams<double> kp, const double* __restrict__ rho_w,
+                         double* __restrict__ aux_w) {
+  const int nx = kp.nx, ny = kp.ny;
+  const size_t N = (size_t)nx * ny;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x = (int)(n % nx), y = (int)(n / nx);
+    double v[9];
+    gather_global(rho_w, nx, ny, x, y, v);
+    aux_w[n] = eos_mu<EOS>(v[0], kp) - kp.kappa * lap9(v);
+  }
+}
+
+struct ObsPartial {
+  double sum_hi, sum_lo, max_u, rho_min, rho_max, du_max, pad0, pad1;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Pass 3: force, velocity (Eq. 6b), exports, per-block partial reductions.
+template <int MODEL, class S, int NT>
+__global__ __launch_bounds__(NT) void k_obs_u(
+    const S* __restrict__ src, const KParams<double> kp,
+    const double* __restrict__ rho_w, const double* __restrict__ aux_w,
+    double* __restrict__ out_rho, double* __restrict__ out_ux,
+    double* __restrict__ out_uy, double* __restrict__ uxp,
+    double* __restrict__ uyp, int have_prev, ObsPartial* __restrict__ part) {
+  const int nx = kp.nx, ny = kp.ny;
+  const size_t N = (size_t)nx * ny;
+  double s_hi = 0.0, s_lo = 0.0, mu = 0.0, rmin = INFINITY, rmax = -INFINITY, du = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x = (int)(n % nx), y = (int)(n / nx);
+    int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    int r0 = y * nx, rm = wrapi(y - 1, ny) * nx, rp = wrapi(y + 1, ny) * nx;
+    double g[9];
+    pull9(src, N, rm, r0, rp, xm, x, xp, g);
+    double rho = rho_w[n];
+    double Fx, Fy;
+    if (MODEL == MODEL_P) {
+      double v[9], sx, sy;
+      gather_global(aux_w, nx, ny, x, y, v);
+      grad_sum(v, sx, sy);
+      Fx = v[0] * sx + kp.fx;
+      Fy = v[0] * sy + kp.fy;
+    } else {
+      double v[9], sx, sy;
+      gather_global(aux_w, nx, ny, x, y, v);
+      grad_sum(v, sx, sy);
+      Fx = -rho * sx + kp.fx;  // F = -rho grad(mu), Eq. 24 gradient
+      Fy = -rho * sy + kp.fy;
+    }
+    double jx = (g[1] - g[3]) + ((g[5] - g[7]) - (g[6] - g[8]));
+    double jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
+    double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho;
+    if (out_rho) out_rho[n] = rho;
+    if (out_ux) out_ux[n] = ux;
+    if (out_uy) out_uy[n] = uy;
+    if (have_prev) {
+      double dx = ux - uxp[n], dy = uy - uyp[n];
+      du = fmax(du, sqrt(dx * dx + dy * dy));
+    }
+    uxp[n] = ux;
+    uyp[n] = uy;
+    // Neumaier accumulation of the mass
+    double s, e;
+    two_sum(s_hi, rho, s, e);
+    s_hi = s;
+    s_lo += e;
+    mu = fmax(mu, sqrt(ux * ux + uy * uy));
+    rmin = fmin(rmin, rho);
+    rmax = fmax(rmax, rho);
+    if (!__builtin_isfinite(rho)) rmin = NAN;
+  }
+  __shared__ ObsPartial sh[NT];
+  sh[threadIdx.x] = ObsPartial{s_hi, s_lo, mu, rmin, rmax, du, 0.0, 0.0};
+  __syncthreads();
+  for (int stride = NT / 2; stride > 0; stride >>= 1) {
+    if ((int)threadIdx.x < stride) {
+      ObsPartial a = sh[threadIdx.x], b = sh[threadIdx.x + stride];
+      double s, e;
+      two_sum(a.sum_hi, b.sum_hi, s, e);
+      a.sum_hi = s;
+      a.sum_lo = a.sum_lo + b.sum_lo + e;
+      a.max_u = fmax(a.max_u, b.max_u);
+      a.rho_min = (a.rho_min != a.rho_min || b.rho_min != b.rho_min) ? NAN : fmin(a.rho_min, b.rho_min);
+      a.rho_max = fmax(a.rho_max, b.rho_max);
+      a.du_max = fmax(a.du_max, b.du_max);
+      sh[threadIdx.x] = a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Pass 4: one workgroup combines the partials in a fixed order and forms the
+// probe observables (Sec. 5.2: pressure jump, equimolar radius).
+template <int EOS, int NT>
+__global__ __launch_bounds__(NT) void k_obs_final(
+    const ObsPartial* __restrict__ part, int nparts, const KParams<double> kp,
+    const double* __restrict__ rho_w, int cx, int cy, double* __restrict__ res) {
+  __shared__ ObsPartial sh[NT];
+  ObsPartial acc{0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0, 0.0};
+  bool nan_min = false;
+  for (int i = threadIdx.x; i < nparts; i += NT) {
+    ObsPartial b = part[i];
+    double s, e;
+    two_sum(acc.sum_hi, b.sum_hi, s, e);
+    acc.sum_hi = s;
+    acc.sum_lo += b.sum_lo + e;
+    acc.max_u = fmax(acc.max_u, b.max_u);
+    if (b.rho_min != b.rho_min) nan_min = true;
+    acc.rho_min = fmin(acc.rho_min, b.rho_min);
+    acc.rho_max = fmax(acc.rho_max, b.rho_max);
+    acc.du_max = fmax(acc.du_max, b.du_max);
+  }
+  if (nan_min) acc.rho_min = NAN;
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int stride = NT / 2; stride > 0; stride >>= 1) {
+    if ((int)threadIdx.x < stride) {
+      ObsPartial a = sh[threadIdx.x], b = sh[threadIdx.x + stride];
+      double s, e;
+      two_sum(a.sum_hi, b.sum_hi, s, e);
+      a.sum_hi = s;
+      a.sum_lo = a.sum_lo + b.sum_lo + e;
+      a.max_u = fmax(a.max_u, b.max_u);
+      a.rho_min = (a.rho_min != a.rho_min || b.rho_min != b.rho_min) ? NAN : fmin(a.rho_min, b.rho_min);
+      a.rho_max = fmax(a.rho_max, b.rho_max);
+      a.du_max = fmax(a.du_max, b.du_max);
+      sh[threadIdx.x] = a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int nx = kp.nx, ny = kp.ny;
+    ObsPartial a = sh[0];
+    double mass = a.sum_hi + a.sum_lo;
+    int xi = wrapi(cx, nx), yi = wrapi(cy, ny);
+    int xo = wrapi(cx + nx / 2, nx), yo = wrapi(cy + ny / 2, ny);
+    double rin = rho_w[(size_t)yi * nx + xi];
+    double rout = rho_w[(size_t)yo * nx + xo];
+    double dp = eos_p<EOS>(rin, kp) - eos_p<EOS>(rout, kp);
+    double excess = mass - (double)nx * (double)ny * rout;
+    double denom = 3.14159265358979323846 * (rin - rout);
+    double q = (denom != 0.0) ? excess / denom : NAN;
+    double req = (q > 0.0) ? sqrt(q) : NAN;
+    res[0] = mass;
+    res[1] = a.max_u;
+    res[2] = a.rho_min;
+    res[3] = a.rho_max;
+    res[4] = rin;
+    res[5] = rout;
+    res[6] = dp;
+    res[7] = req;
+    res[8] = a.du_max;
+  }
+}
+
+}  // namespace lbmk
+
+// =============================================================================
+// Host side
+// =============================================================================
+using namespace lbmk;
+
+namespace {
+
+constexpr int kBX = 256;       // threads (= columns) per strip
+constexpr int kObsThreads = 256;
+constexpr int kObsBlocksMax = 2048;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t pop_bytes, fA, fB, rho_w, aux_w, uxp, uyp, part, flags, result, total;
+  int obs_blocks;
+};
+
+Layout make_layout(const lbm_params* p) {
+  Layout L{};
+  size_t N = (size_t)p->nx * p->ny;
+  size_t es = (p->precision == LBM_FP32_SHIFTED) ? 4 : 8;
+  L.pop_bytes = align_up(9 * N * es);
+  size_t off = 0;
+  L.fA = off; off += L.pop_bytes;
+  L.fB = off; off += L.pop_bytes;
+  L.rho_w = off; off += align_up(N * 8);
+  L.aux_w = off; off += align_up(N * 8);
+  L.uxp = off; off += align_up(N * 8);
+  L.uyp = off; off += align_up(N * 8);
+  L.obs_blocks = (int)std::min<size_t>((N + kObsThreads - 1) / kObsThreads, kObsBlocksMax);
+  L.part = off; off += align_up((size_t)L.obs_blocks * sizeof(ObsPartial));
+  L.flags = off; off += kAlign;
+  L.result = off; off += align_up(16 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+lbm_status validate(const lbm_params* p) {
+  if (!p) return LBM_ERR_INVALID_ARG;
+  if (p->nx < 1 || p->ny < 1) return LBM_ERR_INVALID_ARG;
+  if ((int64_t)p->nx * (int64_t)p->ny >= (int64_t)1 << 31) return LBM_ERR_INVALID_ARG;
+  if (p->model != LBM_MODEL_P && p->model != LBM_MODEL_FE) return LBM_ERR_INVALID_ARG;
+  if (p->eos != LBM_EOS_VDW && p->eos != LBM_EOS_CS) return LBM_ERR_INVALID_ARG;
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED) return LBM_ERR_INVALID_ARG;
+  if (p->reserved0 != 0) return LBM_ERR_INVALID_ARG;
+  if (!finite(p->a) || !finite(p->b) || !finite(p->R) || !finite(p->T)) return LBM_ERR_INVALID_ARG;
+  if (p->a < 0 || p->b <= 0 || p->R <= 0 || p->T <= 0) return LBM_ERR_INVALID_ARG;
+  for (int i = 0; i < 9; ++i)
+    if (!finite(p->tau[i]) || !(p->tau[i] > 0.5)) return LBM_ERR_INVALID_ARG;
+  if (p->tau[3] != p->tau[5] || p->tau[4] != p->tau[6] || p->tau[7] != p->tau[8])
+    return LBM_ERR_INVALID_ARG;
+  if (!finite(p->sigma_li) || !finite(p->kappa_li) || !finite(p->kappa_p) ||
+      !finite(p->kappa) || !finite(p->A) || !finite(p->fx) || !finite(p->fy) ||
+      !finite(p->rho_ref))
+    return LBM_ERR_INVALID_ARG;
+  if (p->model == LBM_MODEL_FE && p->kappa < 0) return LBM_ERR_INVALID_ARG;
+  if (p->A != 0.0) return LBM_ERR_UNSUPPORTED;
+  return LBM_OK;
+}
+
+template <class C>
+KParams<C> make_kparams(const lbm_params* p, double rho_ref, int nstrips,
+                        int nseg, int LY, int xcd_remap) {
+  KParams<C> k{};
+  k.nx = p->nx;
+  k.ny = p->ny;
+  k.nstrips = nstrips;
+  k.nseg = nseg;
+  k.LY = LY;
+  k.xcd_remap = xcd_remap;
+  k.a = (C)p->a;
+  k.b = (C)p->b;
+  k.RT = (C)(p->R * p->T);
+  double le = 1.0 / p->tau[1], lz = 1.0 / p->tau[2], lq = 1.0 / p->tau[4],
+         ln = 1.0 / p->tau[7];
+  k.lam_e = (C)le;
+  k.lam_z = (C)lz;
+  k.lam_q = (C)lq;
+  k.lam_nu = (C)ln;
+  k.hl_e = (C)(1.0 - 0.5 * le);
+  k.hl_z = (C)(1.0 - 0.5 * lz);
+  k.hl_q = (C)(1.0 - 0.5 * lq);
+  k.hl_nu = (C)(1.0 - 0.5 * ln);
+  const double G = -1.0;
+  // Eq. 32: 12 kappa^P sigma^Li |F_int|^2 / (psi^2 (tau - 1/2)); the kernel
+  // multiplies by G^2|S|^2 = |F_int|^2/psi^2.
+  k.sig_e = (C)(12.0 * p->kappa_p * p->sigma_li / (p->tau[1] - 0.5));
+  k.sig_z = (C)(12.0 * p->kappa_p * p->sigma_li / (p->tau[2] - 0.5));
+  // Eq. 30b-31: C_i_ab = C1 G delta + C2 (c c - c_s^2 delta) + kappa^Li (G/2) c c
+  //   = (C1 G - C2/3) delta + (C2 + kappa^Li G/2) c c.
+  double C1 = 5.0 / 6.0 * (p->kappa_p - 1.0);
+  double C2 = 0.5 * G * (1.0 - p->kappa_p);
+  k.qa = (C)(C1 * G - C2 / 3.0);
+  k.qb = (C)(C2 + 0.5 * G * p->kappa_li);
+  k.kappa = (C)p->kappa;
+  k.fx = (C)p->fx;
+  k.fy = (C)p->fy;
+  // rho_ref is chosen by lbm_init so that every shift value below is exact
+  // in float and M s is exact (rho_ref = 36 q for P with q a short float).
+  double s0, sax, sdg;
+  if (p->model == LBM_MODEL_P) {
+    double q = rho_ref / 36.0;
+    s0 = 16.0 * q;
+    sax = 4.0 * q;
+    sdg = q;
+  } else {
+    s0 = rho_ref;
+    sax = 0.0;
+    sdg = 0.0;
+  }
+  k.s0 = (C)s0;
+  k.sax = (C)sax;
+  k.sdg = (C)sdg;
+  k.rho_ref = (C)rho_ref;
+  k.inv_rho_ref = (C)(rho_ref > 0 ? 1.0 / rho_ref : 0.0);
+  k.om_ref = (C)(p->eos == LBM_EOS_CS ? 1.0 - 0.25 * p->b * rho_ref : 1.0 - p->b * rho_ref);
+  return k;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  return atoi(v);
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  hipStream_t stream;
+  char* ws;
+  Layout L;
+  int cur;  // 0: state in fA, 1: state in fB
+  int64_t step;
+  int have_prev;
+  double rho_ref;  // storage shift reference (0 for FP64)
+  int nstrips, nseg, LY, xcd_remap;
+  KParams<double> kd;
+  KParams<float> kf;
+};
+
+namespace {
+
+template <int MODEL, int EOS, class S, class C>
+void launch_step(lbm_ctx* c, const KParams<C>& kp) {
+  const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
+  S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
+  unsigned* flags = (unsigned*)(c->ws + c->L.flags);
+  dim3 grid(c->nstrips * c->nseg), block(kBX);
+  if (MODEL == MODEL_P)
+    hipLaunchKernelGGL((k_step_p<EOS, S, C, kBX>), grid, block, 0, c->stream, src, dst, kp, flags);
+  else
+    hipLaunchKernelGGL((k_step_fe<EOS, S, C, kBX>), grid, block, 0, c->stream, src, dst, kp, flags);
+  c->cur ^= 1;
+}
+
+template <int MODEL, int EOS>
+void step_dispatch_prec(lbm_ctx* c) {
+  if (c->p.precision == LBM_FP64)
+    launch_step<MODEL, EOS, double, double>(c, c->kd);
+  else
+    launch_step<MODEL, EOS, float, float>(c, c->kf);
+}
+
+void step_once(lbm_ctx* c) {
+  if (c->p.model == LBM_MODEL_P) {
+    if (c->p.eos == LBM_EOS_CS) step_dispatch_prec<MODEL_P, EOS_CS>(c);
+    else step_dispatch_prec<MODEL_P, EOS_VDW>(c);
+  } else {
+    if (c->p.eos == LBM_EOS_CS) step_dispatch_prec<MODEL_FE, EOS_CS>(c);
+    else step_dispatch_prec<MODEL_FE, EOS_VDW>(c);
+  }
+}
+
+int grid1d(size_t N) {
+  size_t b = (N + 255) / 256;
+  return (int)std::min<size_t>(std::max<size_t>(b, 1), 4096);
+}
+
+template <class S>
+void launch_init(lbm_ctx* c, const double* rho0) {
+  S* dst = (S*)(c->ws + c->L.fA);
+  size_t N = (size_t)c->p.nx * c->p.ny;
+  if (c->p.model == LBM_MODEL_P)
+    hipLaunchKernelGGL((k_init<MODEL_P, S>), dim3(grid1d(N)), dim3(256), 0, c->stream,
+                       rho0, dst, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+  else
+    hipLaunchKernelGGL((k_init<MODEL_FE, S>), dim3(grid1d(N)), dim3(256), 0, c->stream,
+                       rho0, dst, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+}
+
+template <int MODEL, int EOS, class S>
+void launch_observe(lbm_ctx* c, int cx, int cy, double* d_rho, double* d_ux, double* d_uy) {
+  const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
+  double* rho_w = (double*)(c->ws + c->L.rho_w);
+  double* aux_w = (double*)(c->ws + c->L.aux_w);
+  double* uxp = (double*)(c->ws + c->L.uxp);
+  double* uyp = (double*)(c->ws + c->L.uyp);
+  ObsPartial* part = (ObsPartial*)(c->ws + c->L.part);
+  unsigned* flags = (unsigned*)(c->ws + c->L.flags);
+  double* res = (double*)(c->ws + c->L.result);
+  size_t N = (size_t)c->p.nx * c->p.ny;
+  hipLaunchKernelGGL((k_obs_rho<MODEL, EOS, S>), dim3(grid1d(N)), dim3(256), 0, c->stream,
+                     src, c->kd, rho_w, aux_w, flags);
+  if (MODEL == MODEL_FE)
+    hipLaunchKernelGGL((k_obs_mu<EOS>), dim3(grid1d(N)), dim3(256), 0, c->stream, c->kd,
+                       (const double*)rho_w, aux_w);
+  hipLaunchKernelGGL((k_obs_u<MODEL, S, kObsThreads>), dim3(c->L.obs_blocks),
+                     dim3(kObsThreads), 0, c->stream, src, c->kd, (const double*)rho_w,
+                     (const double*)aux_w, d_rho, d_ux, d_uy, uxp, uyp, c->have_prev, part);
+  hipLaunchKernelGGL((k_obs_final<EOS, kObsThreads>), dim3(1), dim3(kObsThreads), 0,
+                     c->stream, (const ObsPartial*)part, c->L.obs_blocks, c->kd,
+                     (const double*)rho_w, cx, cy, res);
+}
+
+template <int MODEL, int EOS>
+void observe_dispatch_prec(lbm_ctx* c, int cx, int cy, double* r, double* ux, double* uy) {
+  if (c->p.precision == LBM_FP64)
+    launch_observe<MODEL, EOS, double>(c, cx, cy, r, ux, uy);
+  else
+    launch_observe<MODEL, EOS, float>(c, cx, cy, r, ux, uy);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_INVALID_ARG: return "invalid argument";
+    case LBM_ERR_EOS_DOMAIN: return "density outside the equation-of-state domain";
+    case LBM_ERR_UNSUPPORTED: return "unsupported option";
+    case LBM_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case LBM_ERR_HIP: return "HIP runtime error";
+    case LBM_ERR_NO_CONVERGENCE: return "solver did not converge";
+  }
+  return "unknown status";
+}
+
+lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
+  if (!bytes) return LBM_ERR_INVALID_ARG;
+  lbm_status st = validate(p);
+  if (st != LBM_OK) return st;
+  *bytes = make_layout(p).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
+                    const double* d_rho0, void* hip_stream, lbm_ctx** out) {
+  if (!out || !d_rho0) return LBM_ERR_INVALID_ARG;
+  lbm_status st = validate(p);
+  if (st != LBM_OK) return st;
+  Layout L = make_layout(p);
+  if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0)
+    return LBM_ERR_WORKSPACE;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  size_t N = (size_t)p->nx * p->ny;
+
+  // Host copy of rho0 for the domain check and the FP32 reference density.
+  std::vector<double> h(N);
+  if (hipMemcpyAsync(h.data(), d_rho0, N * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return LBM_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return LBM_ERR_HIP;
+  double rmin = INFINITY;
+  for (size_t n = 0; n < N; ++n) {
+    double r = h[n];
+    if (!std::isfinite(r)) return LBM_ERR_EOS_DOMAIN;
+    double lim = (p->eos == LBM_EOS_CS) ? p->b * r / 4.0 : p->b * r;
+    if (!(lim < 1.0) || !(r > 0.0)) return LBM_ERR_EOS_DOMAIN;
+    rmin = std::min(rmin, r);
+  }
+
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ERR_INVALID_ARG;
+  c->p = *p;
+  c->stream = stream;
+  c->ws = (char*)d_workspace;
+  c->L = L;
+  c->cur = 0;
+  c->step = 0;
+  c->have_prev = 0;
+  c->rho_ref = 0.0;
+  if (p->precision == LBM_FP32_SHIFTED) {
+    // Storage shift f^eq(rho_ref, 0) (w_i rho_ref for P, rho_ref delta_i0 for
+    // FE).  The default reference is the smallest initial density: the
+    // stored deviations of the thinnest phase are then near zero, so float
+    // rounding stays a small fraction of every local density (a mid-range
+    // reference would leave the vapour with absolute noise of the order of
+    // 2^-24 rho_ref per step).  Round rho_ref so that rho_ref / 36 carries
+    // at most 20 significant bits: then w_i rho_ref, their sum and M s are
+    // all exact in float and the deviations carry no constant bias.
+    double want = (p->rho_ref > 0.0) ? p->rho_ref : rmin;
+    double q = want / 36.0;
+    int ex;
+    double m = frexp(q, &ex);
+    m = nearbyint(ldexp(m, 20));
+    q = ldexp(m, ex - 20);
+    c->rho_ref = 36.0 * q;
+  }
+
+  c->nstrips = (p->nx + kBX - 1) / kBX;
+  // Segment height: enough tiles to fill 256 CUs several times over, at
+  // least 8 rows so the two halo rows stay a small overhead.
+  int LY = env_int("LBM_LY", 0);
+  if (LY <= 0) {
+    int target_tiles = 2048;
+    int want_seg = std::max(1, target_tiles / c->nstrips);
+    LY = std::max(8, (p->ny + want_seg - 1) / want_seg);
+    LY = std::min(LY, 64);
+  }
+  LY = std::min(LY, p->ny);
+  c->LY = LY;
+  c->nseg = (p->ny + LY - 1) / LY;
+  int ntiles = c->nstrips * c->nseg;
+  c->xcd_remap = (ntiles >= 64 && ntiles % 8 == 0 && env_int("LBM_NO_XCD_REMAP", 0) == 0) ? 1 : 0;
+  c->kd = make_kparams<double>(p, c->rho_ref, c->nstrips, c->nseg, LY, c->xcd_remap);
+  c->kf = make_kparams<float>(p, c->rho_ref, c->nstrips, c->nseg, LY, c->xcd_remap);
+
+  if (hipMemsetAsync(c->ws + L.flags, 0, kAlign, stream) != hipSuccess) {
+    delete c;
+    return LBM_ERR_HIP;
+  }
+  if (p->precision == LBM_FP64) launch_init<double>(c, d_rho0);
+  else launch_init<float>(c, d_rho0);
+  if (hipGetLastError() != hipSuccess) {
+    delete c;
+    return LBM_ERR_HIP;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c || n < 0) return LBM_ERR_INVALID_ARG;
+  for (int64_t k = 0; k < n; ++k) step_once(c);
+  c->step += n;
+  if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
+  return LBM_OK;
+}
+
+lbm_status lbm_observe(lbm_ctx* c, int32_t cx, int32_t cy, lbm_obs* out,
+                       double* d_rho, double* d_ux, double* d_uy) {
+  if (!c || !out) return LBM_ERR_INVALID_ARG;
+  if (c->p.model == LBM_MODEL_P) {
+    if (c->p.eos == LBM_EOS_CS) observe_dispatch_prec<MODEL_P, EOS_CS>(c, cx, cy, d_rho, d_ux, d_uy);
+    else observe_dispatch_prec<MODEL_P, EOS_VDW>(c, cx, cy, d_rho, d_ux, d_uy);
+  } else {
+    if (c->p.eos == LBM_EOS_CS) observe_dispatch_prec<MODEL_FE, EOS_CS>(c, cx, cy, d_rho, d_ux, d_uy);
+    else observe_dispatch_prec<MODEL_FE, EOS_VDW>(c, cx, cy, d_rho, d_ux, d_uy);
+  }
+  if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
+  double res[9];
+  unsigned flags = 0;
+  if (hipMemcpyAsync(res, c->ws + c->L.result, sizeof(res), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return LBM_ERR_HIP;
+  if (hipMemcpyAsync(&flags, c->ws + c->L.flags, sizeof(flags), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return LBM_ERR_HIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM_ERR_HIP;
+  out->step = c->step;
+  out->mass = res[0];
+  out->max_u = res[1];
+  out->rho_min = res[2];
+  out->rho_max = res[3];
+  out->rho_in = res[4];
+  out->rho_out = res[5];
+  out->dp = res[6];
+  out->r_equimolar = res[7];
+  out->du_max = c->have_prev ? res[8] : INFINITY;
+  out->flags = flags;
+  out->reserved = 0;
+  c->have_prev = 1;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, double* d_f) {
+  if (!c || !d_f) return LBM_ERR_INVALID_ARG;
+  size_t N = (size_t)c->p.nx * c->p.ny;
+  const void* src = c->ws + (c->cur ? c->L.fB : c->L.fA);
+  if (c->p.precision == LBM_FP64)
+    hipLaunchKernelGGL((k_get_pop<double>), dim3(grid1d(N)), dim3(256), 0, c->stream,
+                       (const double*)src, d_f, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+  else
+    hipLaunchKernelGGL((k_get_pop<float>), dim3(grid1d(N)), dim3(256), 0, c->stream,
+                       (const float*)src, d_f, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const double* d_f) {
+  if (!c || !d_f) return LBM_ERR_INVALID_ARG;
+  size_t N = (size_t)c->p.nx * c->p.ny;
+  void* dst = c->ws + (c->cur ? c->L.fB : c->L.fA);
+  if (c->p.precision == LBM_FP64)
+    hipLaunchKernelGGL((k_set_pop<double>), dim3(grid1d(N)), dim3(256), 0, c->stream,
+                       d_f, (double*)dst, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+  else
+    hipLaunchKernelGGL((k_set_pop<float>), dim3(grid1d(N)), dim3(256), 0, c->stream,
+                       d_f, (float*)dst, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+  c->have_prev = 0;
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  delete c;
+  return LBM_OK;
+}
+
+}  // extern "C"

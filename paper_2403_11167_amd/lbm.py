@@ -1,0 +1,261 @@
+"""ctypes binding of the C ABI in ``include/lbm.h``.
+
+Argument marshalling only: every step of the lattice Boltzmann update runs in
+the HIP kernels of ``liblbm.so``.  PyTorch supplies device memory (the
+workspace and field buffers) and the stream.  If the shared library is
+missing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+OK, ERR_INVALID_ARG, ERR_EOS_DOMAIN, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NO_CONVERGENCE = (
+    0, -1, -2, -3, -4, -5, -6)
+MODEL_P, MODEL_FE = 0, 1
+EOS_VDW, EOS_CS = 0, 1
+FP64, FP32_SHIFTED = 0, 1
+FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
+
+EXPORTED_SYMBOLS = [
+    "lbm_status_string", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe",
+    "lbm_get_populations", "lbm_set_populations", "lbm_destroy",
+    "lbm_eos_critical", "lbm_maxwell", "lbm_sigma_li_theory", "lbm_fe_planar_theory",
+    "lbm_match_p_to_fe",
+]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("eos", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("R", ctypes.c_double), ("T", ctypes.c_double),
+                ("tau", ctypes.c_double * 9),
+                ("sigma_li", ctypes.c_double), ("kappa_li", ctypes.c_double),
+                ("kappa_p", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("A", ctypes.c_double), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("rho_ref", ctypes.c_double)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("mass", ctypes.c_double),
+                ("max_u", ctypes.c_double), ("rho_min", ctypes.c_double),
+                ("rho_max", ctypes.c_double), ("rho_in", ctypes.c_double),
+                ("rho_out", ctypes.c_double), ("dp", ctypes.c_double),
+                ("r_equimolar", ctypes.c_double), ("du_max", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbm.so (built by ``paper_2403_11167_amd.build``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        D = ctypes.POINTER(ctypes.c_double)
+        P = ctypes.POINTER(Params)
+        L.lbm_status_string.argtypes = [ctypes.c_int]
+        L.lbm_status_string.restype = ctypes.c_char_p
+        L.lbm_workspace_bytes.argtypes = [P, ctypes.POINTER(sz)]
+        L.lbm_init.argtypes = [P, vp, sz, vp, vp, ctypes.POINTER(vp)]
+        L.lbm_step.argtypes = [vp, ctypes.c_int64]
+        L.lbm_observe.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Obs),
+                                  vp, vp, vp]
+        L.lbm_get_populations.argtypes = [vp, vp]
+        L.lbm_set_populations.argtypes = [vp, vp]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_eos_critical.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 3 + [D] * 3
+        L.lbm_maxwell.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 4 + [D] * 3
+        L.lbm_sigma_li_theory.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 4 + [D] * 2
+        L.lbm_fe_planar_theory.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 5 + [D] * 2
+        L.lbm_match_p_to_fe.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 6 + [D] * 3
+        for name in EXPORTED_SYMBOLS:
+            if name != "lbm_status_string":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    return lib().lbm_status_string(int(st)).decode()
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise LbmError(st, what)
+
+
+# ---- host thermodynamics ---------------------------------------------------
+def _outs(n):
+    return [ctypes.c_double() for _ in range(n)]
+
+
+def eos_critical(eos: int, a: float, b: float, R: float):
+    o = _outs(3)
+    _check(lib().lbm_eos_critical(eos, a, b, R, *[ctypes.byref(v) for v in o]), "lbm_eos_critical")
+    return tuple(v.value for v in o)
+
+
+def maxwell(eos: int, a: float, b: float, R: float, T: float):
+    o = _outs(3)
+    _check(lib().lbm_maxwell(eos, a, b, R, T, *[ctypes.byref(v) for v in o]), "lbm_maxwell")
+    return tuple(v.value for v in o)  # rho_l, rho_v, p0
+
+
+def sigma_li_theory(eos: int, a: float, b: float, R: float, T: float):
+    o = _outs(2)
+    _check(lib().lbm_sigma_li_theory(eos, a, b, R, T, *[ctypes.byref(v) for v in o]),
+           "lbm_sigma_li_theory")
+    return tuple(v.value for v in o)  # eps, sigma_li
+
+
+def fe_planar_theory(eos: int, a: float, b: float, R: float, T: float, kappa: float):
+    o = _outs(2)
+    _check(lib().lbm_fe_planar_theory(eos, a, b, R, T, kappa, *[ctypes.byref(v) for v in o]),
+           "lbm_fe_planar_theory")
+    return tuple(v.value for v in o)  # width, gamma
+
+
+def match_p_to_fe(eos: int, a: float, b: float, R: float, T: float, kappa_fe: float,
+                  target_width: float = 0.0):
+    o = _outs(3)
+    _check(lib().lbm_match_p_to_fe(eos, a, b, R, T, kappa_fe, target_width,
+                                   *[ctypes.byref(v) for v in o]), "lbm_match_p_to_fe")
+    return tuple(v.value for v in o)  # sigma_li, kappa_p, kappa_li
+
+
+# ---- simulation --------------------------------------------------------------
+@dataclass
+class Config:
+    """Python mirror of ``lbm_params``."""
+    nx: int
+    ny: int
+    model: int
+    eos: int
+    a: float
+    b: float
+    R: float
+    T: float
+    tau: list = field(default_factory=lambda: [1.0] * 9)
+    sigma_li: float = 0.0
+    kappa_li: float = 0.0
+    kappa_p: float = 1.0
+    kappa: float = 0.0
+    A: float = 0.0
+    fx: float = 0.0
+    fy: float = 0.0
+    precision: int = FP64
+    rho_ref: float = 0.0
+
+    def c_params(self) -> Params:
+        p = Params()
+        p.nx, p.ny, p.model, p.eos = self.nx, self.ny, self.model, self.eos
+        p.precision, p.reserved0 = self.precision, 0
+        p.a, p.b, p.R, p.T = self.a, self.b, self.R, self.T
+        for i, t in enumerate(self.tau):
+            p.tau[i] = float(t)
+        p.sigma_li, p.kappa_li, p.kappa_p = self.sigma_li, self.kappa_li, self.kappa_p
+        p.kappa, p.A, p.fx, p.fy, p.rho_ref = self.kappa, self.A, self.fx, self.fy, self.rho_ref
+        return p
+
+
+def workspace_bytes(cfg: Config) -> int:
+    n = ctypes.c_size_t()
+    p = cfg.c_params()
+    _check(lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)), "lbm_workspace_bytes")
+    return n.value
+
+
+class Simulation:
+    """One lattice on one stream.  ``rho0`` is a torch float64 tensor of shape
+    (ny, nx) on the GPU (or anything with ``data_ptr()``)."""
+
+    def __init__(self, cfg: Config, rho0, stream=None, device=None):
+        import torch
+        self.cfg = cfg
+        self._p = cfg.c_params()
+        if device is None:
+            device = rho0.device
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        nbytes = workspace_bytes(cfg)
+        # torch's allocator returns 256-byte aligned blocks (at least 512 B)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        assert rho0.dtype == torch.float64 and rho0.is_contiguous()
+        assert tuple(rho0.shape) == (cfg.ny, cfg.nx)
+        self._rho0 = rho0
+        ctx = ctypes.c_void_p()
+        st = lib().lbm_init(ctypes.byref(self._p), ctypes.c_void_p(self.workspace.data_ptr()),
+                            nbytes, ctypes.c_void_p(rho0.data_ptr()),
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        _check(st, "lbm_init")
+        self._ctx = ctx
+
+    def step(self, n: int = 1):
+        _check(lib().lbm_step(self._ctx, int(n)), "lbm_step")
+
+    def observe(self, cx: int = 0, cy: int = 0, fields: bool = False):
+        """Observables (dict); with fields=True also (rho, ux, uy) tensors."""
+        import torch
+        o = Obs()
+        rho = ux = uy = None
+        if fields:
+            shp = (self.cfg.ny, self.cfg.nx)
+            rho = torch.empty(shp, dtype=torch.float64, device=self.device)
+            ux = torch.empty_like(rho)
+            uy = torch.empty_like(rho)
+        ptr = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None)
+        _check(lib().lbm_observe(self._ctx, int(cx), int(cy), ctypes.byref(o),
+                                 ptr(rho), ptr(ux), ptr(uy)), "lbm_observe")
+        d = o.as_dict()
+        if fields:
+            return d, (rho, ux, uy)
+        return d
+
+    def populations(self):
+        import torch
+        f = torch.empty((9, self.cfg.ny, self.cfg.nx), dtype=torch.float64, device=self.device)
+        _check(lib().lbm_get_populations(self._ctx, ctypes.c_void_p(f.data_ptr())),
+               "lbm_get_populations")
+        return f
+
+    def set_populations(self, f):
+        assert f.dtype.is_floating_point and f.is_contiguous()
+        _check(lib().lbm_set_populations(self._ctx, ctypes.c_void_p(f.data_ptr())),
+               "lbm_set_populations")
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            lib().lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlups(nodes: int, steps: int, seconds: float) -> float:
+    return nodes * steps / seconds / 1e6 if seconds > 0 else math.nan
