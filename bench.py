@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the fused D2Q9 multiphase step on one MI355X.
+
+Workload (default): 4096 x 4096 periodic lattice, spinodal decomposition
+from the mean density (rho_l + rho_v)/2 with a seeded uniform +-1 %
+perturbation, van der Waals EOS (a = 9/49, b = 2/21, R = 1) at Tr = 0.7;
+both models (pseudopotential and well-balanced free energy), FP64 storage
+for the headline number, FP32-shifted storage reported beside it.  One
+step = one update of each model's lattice.  Inputs are resident in HBM
+before the timed region; the timed region is K back-to-back launches per
+model bracketed by events recorded on the library's stream.
+
+Prints one JSON line (metric, value in MLUPS, roofline of the dominant
+kernel, CPU oracle baseline on the host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+VDW = dict(a=9 / 49, b=2 / 21, R=1.0)
+CS = dict(a=0.25, b=4.0, R=1.0)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbm_kernels.hip",):
+        with open(os.path.join(ROOT, "paper_2403_11167_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str, n: int):
+    """(Config factory, rho0 numpy array, description)."""
+    from paper_2403_11167_amd import inputs, lbm
+    if name == "vdw-spinodal":
+        e, eos, Tr = VDW, lbm.EOS_VDW, 0.7
+    elif name == "cs-spinodal":
+        e, eos, Tr = CS, lbm.EOS_CS, 0.9
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    Tc, _, _ = lbm.eos_critical(eos, e["a"], e["b"], e["R"])
+    T = Tr * Tc
+    rl, rv, _ = lbm.maxwell(eos, e["a"], e["b"], e["R"], T)
+    rho0 = inputs.spinodal(n, n, 0.5 * (rl + rv), 0.01, seed=3)
+
+    def cfg(model: int, precision: int) -> "lbm.Config":
+        tau = [1.0] * 9
+        if model == lbm.MODEL_FE:
+            tau[1] = 0.75  # nu = c_s^2/2, nu_B = c_s^2/3 (Sec. 5.1)
+            return lbm.Config(n, n, model, eos, e["a"], e["b"], e["R"], T, tau=tau, kappa=0.5,
+                              precision=precision)
+        return lbm.Config(n, n, model, eos, e["a"], e["b"], e["R"], T, tau=tau,
+                          precision=precision)
+
+    desc = (f"{n}x{n} periodic spinodal decomposition, {'vdW a=9/49 b=2/21' if eos == lbm.EOS_VDW else 'C-S a=0.25 b=4'}"
+            f" R=1, Tr={Tr}, rho0=(rho_l+rho_v)/2*(1+0.01*U(-1,1)) seed 3")
+    return cfg, rho0, desc
+
+
+def time_variant(cfg, rho0_dev, steps: int, warmup: int):
+    """(seconds for `steps` launches on the library's stream, final obs)."""
+    import torch
+    from paper_2403_11167_amd import lbm
+    sim = lbm.Simulation(cfg, rho0_dev)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    sim.step(steps)
+    stop.record(sim.stream)
+    torch.cuda.synchronize()
+    seconds = start.elapsed_time(stop) / 1e3
+    obs = sim.observe(cfg.nx // 2, cfg.ny // 2)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return seconds, obs
+
+
+def cpu_baseline(cfg_factory, rho0, target_seconds: float):
+    """The FP64 oracle, as it stands, on the host cores: both models on the
+    same 4096^2 initial state, k steps each with k chosen so that the sample
+    takes about `target_seconds`."""
+    import oracle
+    from paper_2403_11167_amd import lbm
+
+    def oparams(c):
+        return oracle.OracleParams(c.nx, c.ny, c.model, c.eos, c.a, c.b, c.R, c.T, tau=list(c.tau),
+                                   sigma_li=c.sigma_li, kappa_li=c.kappa_li, kappa_p=c.kappa_p,
+                                   kappa=c.kappa)
+
+    N = rho0.size
+    total_nodes, total_t, steps_done = 0, 0.0, {}
+    for model in (lbm.MODEL_P, lbm.MODEL_FE):
+        s = oracle.Simulation(oparams(cfg_factory(model, lbm.FP64)), rho0)
+        t0 = time.perf_counter()
+        s.step(1)
+        t1 = time.perf_counter() - t0
+        k = max(1, int(target_seconds / 2 / max(t1, 1e-9)) - 1)
+        t0 = time.perf_counter()
+        s.step(k)
+        dt = time.perf_counter() - t0
+        total_nodes += N * (k + 1)
+        total_t += dt + t1
+        steps_done["P" if model == lbm.MODEL_P else "FE"] = k + 1
+        del s
+    return dict(value=total_nodes / total_t / 1e6, unit="MLUPS", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"{int(math.sqrt(N))}^2 lattice of the same workload, FP64, "
+                       f"{steps_done['P']} P steps and {steps_done['FE']} FE steps from the "
+                       f"initial state ({total_t:.1f} s)")
+
+
+def load_traffic(kernel: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--workload", default="vdw-spinodal", choices=["vdw-spinodal", "cs-spinodal"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the lattice would shard by 2-D domain decomposition, not implemented here.",
+              file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    from paper_2403_11167_amd import lbm
+    lbm.lib()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+
+    if args.copy_calibration:
+        nbytes = 1 << 31
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": nbytes, "launches": 3}))
+        return
+
+    cfg_factory, rho0, desc = workload(args.workload, args.n)
+    rho0_dev = torch.from_numpy(rho0).to(dev)
+    N = args.n * args.n
+    K, W = args.steps, args.warmup
+
+    variants = {}
+    precs = [("fp64", lbm.FP64)] + ([] if args.no_fp32 else [("fp32_shifted", lbm.FP32_SHIFTED)])
+    for pname, prec in precs:
+        for mname, model in (("P", lbm.MODEL_P), ("FE", lbm.MODEL_FE)):
+            secs, obs = time_variant(cfg_factory(model, prec), rho0_dev, K, W)
+            es = 8 if prec == lbm.FP64 else 4
+            ms = secs * 1e3 / K
+            variants[f"{mname}_{pname}"] = dict(
+                mlups=N * K / secs / 1e6, ms_per_step=ms,
+                hbm_gbs_algorithmic=18 * es * N / (ms * 1e-3) / 1e9,
+                flags=int(obs["flags"]), finite=bool(math.isfinite(obs["mass"])))
+            print(f"# {mname} {pname}: {ms:.4f} ms/step, {N * K / secs / 1e6:.0f} MLUPS, "
+                  f"flags {obs['flags']}", file=sys.stderr, flush=True)
+
+    t_p = variants["P_fp64"]["ms_per_step"]
+    t_fe = variants["FE_fp64"]["ms_per_step"]
+    ms_per_step = t_p + t_fe
+    value = 2 * N / (ms_per_step * 1e-3) / 1e6
+
+    dom = "P" if t_p >= t_fe else "FE"
+    dom_ms = max(t_p, t_fe)
+    kernel_name = "k_step_p<double>" if dom == "P" else "k_step_fe<double>"
+    algo_bytes = 18 * 8 * N  # 9 population reads + 9 writes, FP64
+    achieved = algo_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=load_traffic(kernel_name),
+                    kernel=kernel_name, algorithmic_bytes_per_launch=algo_bytes,
+                    launch_ms=dom_ms)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg_factory, rho0, args.cpu_seconds)
+
+    line = {
+        "metric": "MLUPS (4096^2 D2Q9 multiphase step, both models) + HBM GB/s % peak",
+        "value": value,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "lattice": f"{args.n}x{args.n}",
+                   "lbm_models": ["pseudopotential (P)", "well-balanced free energy (FE)"],
+                   "step": "one update of each model's lattice",
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

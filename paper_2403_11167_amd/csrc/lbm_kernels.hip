@@ -348,6 +348,23 @@ __device__ __forceinline__ int tile_index(int xcd_remap) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Sticky-flag commit at the end of a kernel, called by every thread of the
+// workgroup: OR the flag bits across each wavefront by ballot, then across
+// the workgroup in LDS, and issue one global atomic per workgroup, only if
+// it adds bits not yet set (a run that has gone non-finite would otherwise
+// issue one atomic per node and step).
+__device__ __forceinline__ void commit_flags(unsigned fl, unsigned* __restrict__ flags,
+                                             unsigned* s_flag) {
+  unsigned long long b0 = __ballot(fl & 1u), b1 = __ballot(fl & 2u), b2 = __ballot(fl & 4u);
+  unsigned w = (b0 ? 1u : 0u) | (b1 ? 2u : 0u) | (b2 ? 4u : 0u);
+  if (w && (threadIdx.x & 63) == 0) atomicOr(s_flag, w);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned v = *s_flag;
+    if (v && (v & ~__atomic_load_n(flags, __ATOMIC_RELAXED))) atomicOr(flags, v);
+  }
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
@@ -360,6 +377,8 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
                                                const KParams<C> kp,
                                                unsigned* __restrict__ flags) {
   __shared__ C psi_s[4][BX + 2];
+  __shared__ unsigned s_flag;
+  if (threadIdx.x == 0) s_flag = 0u;
   const int nx = kp.nx, ny = kp.ny;
   const size_t N = (size_t)nx * ny;
   const int tile = tile_index(kp.xcd_remap);
@@ -453,7 +472,7 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
       drho_c = drho_n;
     }
   }
-  if (fl) atomicOr(flags, fl);
+  commit_flags(fl, flags, &s_flag);
 }
 
 // ---- free-energy step -------------------------------------------------------
@@ -464,6 +483,8 @@ __global__ __launch_bounds__(BX) void k_step_fe(const S* __restrict__ src,
                                                 unsigned* __restrict__ flags) {
   __shared__ C rho_s[8][BX + 4];
   __shared__ C mu_s[4][BX + 2];
+  __shared__ unsigned s_flag;
+  if (threadIdx.x == 0) s_flag = 0u;
   const int nx = kp.nx, ny = kp.ny;
   const size_t N = (size_t)nx * ny;
   const int tile = tile_index(kp.xcd_remap);
@@ -568,7 +589,7 @@ __global__ __launch_bounds__(BX) void k_step_fe(const S* __restrict__ src,
       d1 = d2;
     }
   }
-  if (fl) atomicOr(flags, fl);
+  commit_flags(fl, flags, &s_flag);
 }
 
 // ---- initial state ------------------------------------------------------------
@@ -636,6 +657,9 @@ template <int MODEL, int EOS, class S>
 __global__ void k_obs_rho(const S* __restrict__ src, const KParams<double> kp,
                           double* __restrict__ rho_w, double* __restrict__ aux_w,
                           unsigned* __restrict__ flags) {
+  __shared__ unsigned s_flag;
+  if (threadIdx.x == 0) s_flag = 0u;
+  __syncthreads();
   const int nx = kp.nx, ny = kp.ny;
   const size_t N = (size_t)nx * ny;
   unsigned fl = 0;
@@ -651,7 +675,7 @@ __global__ void k_obs_rho(const S* __restrict__ src, const KParams<double> kp,
     rho_w[n] = rho;
     if (MODEL == MODEL_P) aux_w[n] = psi_of<EOS>(rho, kp, fl);
   }
-  if (fl) atomicOr(flags, fl);
+  commit_flags(fl, flags, &s_flag);
 }
 
 template <class C>
