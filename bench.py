@@ -3,9 +3,14 @@
 
 Workload (default): 4096 x 4096 periodic lattice, spinodal decomposition
 from the mean density (rho_l + rho_v)/2 with a seeded uniform +-1 %
-perturbation, van der Waals EOS (a = 9/49, b = 2/21, R = 1) at Tr = 0.7;
-both models (pseudopotential and well-balanced free energy), FP64 storage
-for the headline number, FP32-shifted storage reported beside it.  One
+perturbation, Carnahan-Starling EOS (a = 0.25, b = 4, R = 1, the paper's
+EOS and droplet parameters) at Tr = 0.85; both models (pseudopotential and
+well-balanced free energy), FP64 storage for the headline number,
+FP32-shifted storage reported beside it.  ``--workload vdw-spinodal`` runs
+the van der Waals (a = 9/49, b = 2/21, R = 1) Tr = 0.7 variant, which
+leaves the EOS domain within ~50 steps on both models; its lines carry the
+non-finite flags and its free-energy timing is inflated by the special-value
+paths of log on non-finite data.  One
 step = one update of each model's lattice.  Inputs are resident in HBM
 before the timed region; the timed region is K back-to-back launches per
 model bracketed by events recorded on the library's stream.
@@ -46,7 +51,7 @@ def workload(name: str, n: int):
     if name == "vdw-spinodal":
         e, eos, Tr = VDW, lbm.EOS_VDW, 0.7
     elif name == "cs-spinodal":
-        e, eos, Tr = CS, lbm.EOS_CS, 0.9
+        e, eos, Tr = CS, lbm.EOS_CS, 0.85
     else:
         raise SystemExit(f"unknown workload {name}")
     Tc, _, _ = lbm.eos_critical(eos, e["a"], e["b"], e["R"])
@@ -143,7 +148,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--workload", default="vdw-spinodal", choices=["vdw-spinodal", "cs-spinodal"])
+    ap.add_argument("--workload", default="cs-spinodal", choices=["cs-spinodal", "vdw-spinodal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-fp32", action="store_true")

@@ -3,8 +3,14 @@
 // Czelusniak et al., arXiv 2403.11167).  See include/lbm.h for the contract.
 //
 // Data layout in HBM
-//   Populations: structure of arrays, plane i (Eq. 2 order) of nx*ny values,
-//   x fastest.  What is stored is the post-collision, pre-streaming field
+//   Populations: array of structures of arrays with 64-node blocks.  Row y
+//   is split into blocks of 64 columns; for each block the nine velocity
+//   chunks of 64 values (Eq. 2 order) are contiguous, so element (i, x, y)
+//   sits at y * rowpitch + (x / 64) * 576 + 64 i + x % 64 with rowpitch =
+//   576 ceil(nx / 64).  A wavefront (64 lanes = one block) reads each
+//   velocity chunk as one coalesced segment (two when shifted by one
+//   column), and a workgroup's row is a few contiguous regions instead of
+//   nine plane streams.  What is stored is the post-collision, pre-streaming field
 //   g*_i(x) = f*_i(x) - s_i, where s_i = f_i^eq(rho_ref, u = 0) of the model
 //   (w_i rho_ref for the pseudopotential, rho_ref delta_i0 for the free
 //   energy) and rho_ref = 0 for FP64 storage.  A step pulls
@@ -47,6 +53,7 @@ struct KParams {
   int nstrips, nseg, LY;
   int xcd_remap;  // 1: map workgroups so that each XCD gets a contiguous
                   // band of tiles (neighbouring tiles share its L2)
+  int rowpitch;   // population elements per lattice row (576 per 64 columns)
   C a, b, RT;
   C lam_e, lam_z, lam_q, lam_nu;  // 1/tau of the e, zeta, q, p rows (Eq. 3)
   C hl_e, hl_z, hl_q, hl_nu;      // 1 - lam/2 (Eq. 1 forcing factor)
@@ -159,22 +166,39 @@ __device__ __forceinline__ C psi_of(C rho, const KParams<C>& kp, unsigned& fl) {
 }
 
 // ---- streaming ------------------------------------------------------------
+// Population loads and stores.  NT bit 0: non-temporal stores, bit 1:
+// non-temporal loads (each population is read and written once per step;
+// the working set is far larger than L2 and the infinity cache).
+template <int NT, class S>
+__device__ __forceinline__ S ld(const S* p) {
+  if constexpr (NT & 2) return __builtin_nontemporal_load(p); else return *p;
+}
+template <int NT, class S>
+__device__ __forceinline__ void st(S* p, S v) {
+  if constexpr (NT & 1) __builtin_nontemporal_store(v, p); else *p = v;
+}
+
 // Pulled deviations g_i(x, y) = g*_i(x - c_i) for one node; rm / r0 / rp are
 // the row offsets of y-1, y, y+1 and xm / x / xp the columns x-1, x, x+1
 // (periodic wrap already applied).
-template <class S, class C>
-__device__ __forceinline__ void pull9(const S* __restrict__ src, size_t N,
-                                      int rm, int r0, int rp, int xm, int x,
-                                      int xp, C g[9]) {
-  g[0] = (C)src[r0 + x];
-  g[1] = (C)src[N + r0 + xm];
-  g[2] = (C)src[2 * N + rm + x];
-  g[3] = (C)src[3 * N + r0 + xp];
-  g[4] = (C)src[4 * N + rp + x];
-  g[5] = (C)src[5 * N + rm + xm];
-  g[6] = (C)src[6 * N + rm + xp];
-  g[7] = (C)src[7 * N + rp + xp];
-  g[8] = (C)src[8 * N + rp + xm];
+// Column offset of x inside a row of the blocked layout.
+__device__ __forceinline__ int colo(int x) { return (x >> 6) * 576 + (x & 63); }
+
+// Pulled deviations g_i(x, y) = g*_i(x - c_i) for one node: rm / r0 / rp are
+// the row offsets of y-1, y, y+1 and cm / c0 / cp the column offsets of
+// x-1, x, x+1 (periodic wrap already applied); velocity i adds 64 i.
+template <class S, class C, int NT = 0>
+__device__ __forceinline__ void pull9(const S* __restrict__ src, int rm, int r0,
+                                      int rp, int cm, int c0, int cp, C g[9]) {
+  g[0] = (C)ld<NT>(&src[r0 + c0]);
+  g[1] = (C)ld<NT>(&src[r0 + cm + 64]);
+  g[2] = (C)ld<NT>(&src[rm + c0 + 128]);
+  g[3] = (C)ld<NT>(&src[r0 + cp + 192]);
+  g[4] = (C)ld<NT>(&src[rp + c0 + 256]);
+  g[5] = (C)ld<NT>(&src[rm + cm + 320]);
+  g[6] = (C)ld<NT>(&src[rm + cp + 384]);
+  g[7] = (C)ld<NT>(&src[rp + cp + 448]);
+  g[8] = (C)ld<NT>(&src[rp + cm + 512]);
 }
 
 template <class C>
@@ -371,8 +395,8 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 }
 
 // ---- pseudopotential step ---------------------------------------------------
-template <int EOS, class S, class C, int BX>
-__global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
+template <int EOS, class S, class C, int BX, int NT, int WPE>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_step_p(const S* __restrict__ src,
                                                S* __restrict__ dst,
                                                const KParams<C> kp,
                                                unsigned* __restrict__ flags) {
@@ -392,18 +416,20 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
   const int x = x0 + (active ? t : 0);
   const int xm = (x == 0) ? nx - 1 : x - 1;
   const int xp = (x == nx - 1) ? 0 : x + 1;
+  const int cm = colo(xm), c0 = colo(x), cp = colo(xp);
   // halo column handled by lanes 0 (left) and 1 (right)
   const bool hl = t < 2;
   const int hx = (t == 0) ? wrapi(x0 - 1, nx) : wrapi(x0 + w, nx);
   const int hxm = (hx == 0) ? nx - 1 : hx - 1;
   const int hxp = (hx == nx - 1) ? 0 : hx + 1;
+  const int hcm = colo(hxm), hc0 = colo(hx), hcp = colo(hxp);
   const int hj = (t == 0) ? 0 : w + 1;
 
   unsigned fl = 0;
   C gc[9], gn[9];
   C drho_c = C(0), drho_n = C(0);
 
-  auto rowoff = [&](int y) { return wrapi(y, ny) * nx; };
+  auto rowoff = [&](int y) { return wrapi(y, ny) * kp.rowpitch; };
 
   // Rows y0-1 (psi only) and y0 (psi and populations).
   for (int r = 0; r < 2; ++r) {
@@ -411,7 +437,7 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
     const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
     if (active) {
       C g[9];
-      pull9(src, N, rm, r0, rp, xm, x, xp, g);
+      pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
       C dr = sum9(g);
       C rho = kp.rho_ref + dr;
       fl |= domain_flags<MODEL_P, EOS>(rho, kp);
@@ -423,7 +449,7 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
     }
     if (hl) {
       C g[9];
-      pull9(src, N, rm, r0, rp, hxm, hx, hxp, g);
+      pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, g);
       C rho = kp.rho_ref + sum9(g);
       psi_s[r][hj] = psi_of<EOS>(rho, kp, fl);
     }
@@ -437,7 +463,7 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
       const int r0 = rowoff(yn), rm = rowoff(yn - 1), rp = rowoff(yn + 1);
       C* row = psi_s[(k + 2) & 3];
       if (active) {
-        pull9(src, N, rm, r0, rp, xm, x, xp, gn);
+        pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, gn);
         drho_n = sum9(gn);
         C rho = kp.rho_ref + drho_n;
         fl |= domain_flags<MODEL_P, EOS>(rho, kp);
@@ -445,7 +471,7 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
       }
       if (hl) {
         C g[9];
-        pull9(src, N, rm, r0, rp, hxm, hx, hxp, g);
+        pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, g);
         C rho = kp.rho_ref + sum9(g);
         row[hj] = psi_of<EOS>(rho, kp, fl);
       }
@@ -464,9 +490,9 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
       q_terms(v, kp.qa, kp.qb, qs, qd, qxy);
       C rho = kp.rho_ref + drho_c;
       collide<MODEL_P>(gc, drho_c, rho, Fx, Fy, K, qs, qd, qxy, kp);
-      const int off = wrapi(y, ny) * nx + x;
+      const int off = wrapi(y, ny) * kp.rowpitch + c0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) dst[i * N + off] = (S)gc[i];
+      for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)gc[i]);
 #pragma unroll
       for (int i = 0; i < 9; ++i) gc[i] = gn[i];
       drho_c = drho_n;
@@ -475,9 +501,107 @@ __global__ __launch_bounds__(BX) void k_step_p(const S* __restrict__ src,
   commit_flags(fl, flags, &s_flag);
 }
 
+// Software-pipelined variant: the populations of row y+2 (interior and
+// halo columns) are loaded at the top of the iteration that collides row y
+// and only consumed one iteration later, so their memory latency overlaps
+// the psi row, the barrier and the collision in between.
+template <int EOS, class S, class C, int BX, int NT, int WPE>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_step_p_pipe(const S* __restrict__ src,
+                                                    S* __restrict__ dst,
+                                                    const KParams<C> kp,
+                                                    unsigned* __restrict__ flags) {
+  __shared__ C psi_s[4][BX + 2];
+  __shared__ unsigned s_flag;
+  if (threadIdx.x == 0) s_flag = 0u;
+  const int nx = kp.nx, ny = kp.ny;
+  const size_t N = (size_t)nx * ny;
+  const int tile = tile_index(kp.xcd_remap);
+  const int strip = tile % kp.nstrips, seg = tile / kp.nstrips;
+  const int x0 = strip * BX;
+  const int w = min(BX, nx - x0);
+  const int y0 = seg * kp.LY;
+  const int ly = min(kp.LY, ny - y0);
+  const int t = threadIdx.x;
+  const bool active = t < w;
+  const int x = x0 + (active ? t : 0);
+  const int xm = (x == 0) ? nx - 1 : x - 1;
+  const int xp = (x == nx - 1) ? 0 : x + 1;
+  const int cm = colo(xm), c0 = colo(x), cp = colo(xp);
+  const bool hl = t < 2;
+  const int hx = (t == 0) ? wrapi(x0 - 1, nx) : wrapi(x0 + w, nx);
+  const int hxm = (hx == 0) ? nx - 1 : hx - 1;
+  const int hxp = (hx == nx - 1) ? 0 : hx + 1;
+  const int hcm = colo(hxm), hc0 = colo(hx), hcp = colo(hxp);
+  const int hj = (t == 0) ? 0 : w + 1;
+
+  unsigned fl = 0;
+  C gc[9], gn[9], hn[9];
+  C drho_c = C(0);
+
+  auto rowoff = [&](int y) { return wrapi(y, ny) * kp.rowpitch; };
+  auto pull_row = [&](int y, C g[9], C h[9]) {
+    const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
+    if (active) pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
+    if (hl) pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
+  };
+  // psi row from pulled populations; returns the interior density deviation
+  auto psi_row = [&](const C g[9], const C h[9], C* row) {
+    C dr = C(0);
+    if (active) {
+      dr = sum9(g);
+      C rho = kp.rho_ref + dr;
+      fl |= domain_flags<MODEL_P, EOS>(rho, kp);
+      row[t + 1] = psi_of<EOS>(rho, kp, fl);
+    }
+    if (hl) row[hj] = psi_of<EOS>(kp.rho_ref + sum9(h), kp, fl);
+    return dr;
+  };
+
+  {
+    C g[9], h[9];
+    pull_row(y0 - 1, g, h);
+    psi_row(g, h, psi_s[0]);
+    pull_row(y0, gc, h);
+    drho_c = psi_row(gc, h, psi_s[1]);
+    pull_row(y0 + 1, gn, hn);
+  }
+
+  for (int k = 0; k < ly; ++k) {
+    const int y = y0 + k;
+    C g2[9], h2[9];
+    if (k + 2 <= ly) pull_row(y + 2, g2, h2);
+    C drho_n = psi_row(gn, hn, psi_s[(k + 2) & 3]);
+    __syncthreads();
+    if (active) {
+      C v[9];
+      gather(psi_s[k & 3], psi_s[(k + 1) & 3], psi_s[(k + 2) & 3], t + 1, v);
+      C sx, sy;
+      grad_sum(v, sx, sy);
+      C Fx = v[0] * sx + kp.fx;
+      C Fy = v[0] * sy + kp.fy;
+      C K = sx * sx + sy * sy;
+      C qs, qd, qxy;
+      q_terms(v, kp.qa, kp.qb, qs, qd, qxy);
+      C rho = kp.rho_ref + drho_c;
+      collide<MODEL_P>(gc, drho_c, rho, Fx, Fy, K, qs, qd, qxy, kp);
+      const int off = wrapi(y, ny) * kp.rowpitch + c0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)gc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      gc[i] = gn[i];
+      gn[i] = g2[i];
+      hn[i] = h2[i];
+    }
+    drho_c = drho_n;
+  }
+  commit_flags(fl, flags, &s_flag);
+}
+
 // ---- free-energy step -------------------------------------------------------
-template <int EOS, class S, class C, int BX>
-__global__ __launch_bounds__(BX) void k_step_fe(const S* __restrict__ src,
+template <int EOS, class S, class C, int BX, int NT, int WPE>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_step_fe(const S* __restrict__ src,
                                                 S* __restrict__ dst,
                                                 const KParams<C> kp,
                                                 unsigned* __restrict__ flags) {
@@ -498,12 +622,14 @@ __global__ __launch_bounds__(BX) void k_step_fe(const S* __restrict__ src,
   const int x = x0 + (active ? t : 0);
   const int xm = (x == 0) ? nx - 1 : x - 1;
   const int xp = (x == nx - 1) ? 0 : x + 1;
+  const int cm = colo(xm), c0 = colo(x), cp = colo(xp);
   // rho halo columns x0-2, x0-1, x0+w, x0+w+1 on lanes 0..3
   const bool hr = t < 4;
   const int hoff = (t < 2) ? (t - 2) : (w + t - 2);
   const int hx = wrapi(x0 + hoff, nx);
   const int hxm = (hx == 0) ? nx - 1 : hx - 1;
   const int hxp = (hx == nx - 1) ? 0 : hx + 1;
+  const int hcm = colo(hxm), hc0 = colo(hx), hcp = colo(hxp);
   const int hj = hoff + 2;  // LDS index of the halo column in rho_s
   // mu halo columns x0-1 (lane 0) and x0+w (lane 1)
   const bool hm = t < 2;
@@ -513,21 +639,21 @@ __global__ __launch_bounds__(BX) void k_step_fe(const S* __restrict__ src,
   C g0[9], g1[9], g2[9];
   C d0 = C(0), d1 = C(0), d2 = C(0);
 
-  auto rowoff = [&](int y) { return wrapi(y, ny) * nx; };
+  auto rowoff = [&](int y) { return wrapi(y, ny) * kp.rowpitch; };
 
   // density of row y into ring slot r (and the populations of interior lanes)
   auto load_row = [&](int y, int slot, C g[9], C& dr) {
     const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
     C* row = rho_s[slot & 7];
     if (active) {
-      pull9(src, N, rm, r0, rp, xm, x, xp, g);
+      pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
       dr = sum9(g);
       fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dr, kp);
       row[t + 2] = dr;
     }
     if (hr) {
       C h[9];
-      pull9(src, N, rm, r0, rp, hxm, hx, hxp, h);
+      pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
       row[hj] = sum9(h);
     }
   };
@@ -580,9 +706,9 @@ __global__ __launch_bounds__(BX) void k_step_fe(const S* __restrict__ src,
       C Fx = -rho * gmx + kp.fx;  // F = -rho grad(mu)
       C Fy = -rho * gmy + kp.fy;
       collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp);
-      const int off = wrapi(y, ny) * nx + x;
+      const int off = wrapi(y, ny) * kp.rowpitch + c0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) dst[i * N + off] = (S)g0[i];
+      for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)g0[i]);
 #pragma unroll
       for (int i = 0; i < 9; ++i) { g0[i] = g1[i]; g1[i] = g2[i]; }
       d0 = d1;
@@ -597,7 +723,7 @@ __global__ __launch_bounds__(BX) void k_step_fe(const S* __restrict__ src,
 // yields f_i(x) = f^eq_i(rho0(x), 0) (Eq. 4: w_i rho; Eq. 20: rho delta_i0).
 template <int MODEL, class S>
 __global__ void k_init(const double* __restrict__ rho0, S* __restrict__ dst,
-                       int nx, int ny, double s0, double sax, double sdg) {
+                       int nx, int ny, int rowpitch, double s0, double sax, double sdg) {
   const size_t N = (size_t)nx * ny;
   const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -611,7 +737,7 @@ __global__ void k_init(const double* __restrict__ rho0, S* __restrict__ dst,
       double r = rho0[(size_t)ys * nx + xs];
       double feq = (MODEL == MODEL_P) ? wt[i] * r : ((i == 0) ? r : 0.0);
       double s = (i == 0) ? s0 : (i < 5 ? sax : sdg);
-      dst[i * N + n] = (S)(feq - s);
+      dst[y * rowpitch + colo(x) + 64 * i] = (S)(feq - s);
     }
   }
 }
@@ -619,7 +745,7 @@ __global__ void k_init(const double* __restrict__ rho0, S* __restrict__ dst,
 // ---- population import / export (post-streaming f_i(x, t)) ----------------
 template <class S>
 __global__ void k_get_pop(const S* __restrict__ src, double* __restrict__ f,
-                          int nx, int ny, double s0, double sax, double sdg) {
+                          int nx, int ny, int rowpitch, double s0, double sax, double sdg) {
   const size_t N = (size_t)nx * ny;
   const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -629,14 +755,14 @@ __global__ void k_get_pop(const S* __restrict__ src, double* __restrict__ f,
     for (int i = 0; i < 9; ++i) {
       int xs = wrapi(x - cx[i], nx), ys = wrapi(y - cy[i], ny);
       double s = (i == 0) ? s0 : (i < 5 ? sax : sdg);
-      f[i * N + n] = s + (double)src[i * N + (size_t)ys * nx + xs];
+      f[i * N + n] = s + (double)src[ys * rowpitch + colo(xs) + 64 * i];
     }
   }
 }
 
 template <class S>
 __global__ void k_set_pop(const double* __restrict__ f, S* __restrict__ dst,
-                          int nx, int ny, double s0, double sax, double sdg) {
+                          int nx, int ny, int rowpitch, double s0, double sax, double sdg) {
   const size_t N = (size_t)nx * ny;
   const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -646,7 +772,7 @@ __global__ void k_set_pop(const double* __restrict__ f, S* __restrict__ dst,
     for (int i = 0; i < 9; ++i) {
       int xs = wrapi(x + cx[i], nx), ys = wrapi(y + cy[i], ny);
       double s = (i == 0) ? s0 : (i < 5 ? sax : sdg);
-      dst[i * N + n] = (S)(f[i * N + (size_t)ys * nx + xs] - s);
+      dst[y * rowpitch + colo(x) + 64 * i] = (S)(f[i * N + (size_t)ys * nx + xs] - s);
     }
   }
 }
@@ -667,9 +793,10 @@ __global__ void k_obs_rho(const S* __restrict__ src, const KParams<double> kp,
        n += (size_t)gridDim.x * blockDim.x) {
     int x = (int)(n % nx), y = (int)(n / nx);
     int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
-    int r0 = y * nx, rm = wrapi(y - 1, ny) * nx, rp = wrapi(y + 1, ny) * nx;
+    const int rw = kp.rowpitch;
+    int r0 = y * rw, rm = wrapi(y - 1, ny) * rw, rp = wrapi(y + 1, ny) * rw;
     double g[9];
-    pull9(src, N, rm, r0, rp, xm, x, xp, g);
+    pull9(src, rm, r0, rp, colo(xm), colo(x), colo(xp), g);
     double rho = kp.rho_ref + sum9(g);
     fl |= domain_flags<MODEL, EOS>(rho, kp);
     rho_w[n] = rho;
@@ -734,9 +861,10 @@ __global__ __launch_bounds__(NT) void k_obs_u(
        n += (size_t)gridDim.x * blockDim.x) {
     int x = (int)(n % nx), y = (int)(n / nx);
     int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
-    int r0 = y * nx, rm = wrapi(y - 1, ny) * nx, rp = wrapi(y + 1, ny) * nx;
+    const int rw = kp.rowpitch;
+    int r0 = y * rw, rm = wrapi(y - 1, ny) * rw, rp = wrapi(y + 1, ny) * rw;
     double g[9];
-    pull9(src, N, rm, r0, rp, xm, x, xp, g);
+    pull9(src, rm, r0, rp, colo(xm), colo(x), colo(xp), g);
     double rho = rho_w[n];
     double Fx, Fy;
     if (MODEL == MODEL_P) {
@@ -875,6 +1003,9 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Population elements per lattice row in the blocked layout.
+size_t row_pitch(int nx) { return (size_t)576 * (size_t)((nx + 63) / 64); }
+
 struct Layout {
   size_t pop_bytes, fA, fB, rho_w, aux_w, uxp, uyp, part, flags, result, total;
   int obs_blocks;
@@ -884,7 +1015,7 @@ Layout make_layout(const lbm_params* p) {
   Layout L{};
   size_t N = (size_t)p->nx * p->ny;
   size_t es = (p->precision == LBM_FP32_SHIFTED) ? 4 : 8;
-  L.pop_bytes = align_up(9 * N * es);
+  L.pop_bytes = align_up((size_t)p->ny * row_pitch(p->nx) * es);
   size_t off = 0;
   L.fA = off; off += L.pop_bytes;
   L.fB = off; off += L.pop_bytes;
@@ -906,6 +1037,8 @@ lbm_status validate(const lbm_params* p) {
   if (!p) return LBM_ERR_INVALID_ARG;
   if (p->nx < 1 || p->ny < 1) return LBM_ERR_INVALID_ARG;
   if ((int64_t)p->nx * (int64_t)p->ny >= (int64_t)1 << 31) return LBM_ERR_INVALID_ARG;
+  // population offsets are 32-bit: ny * rowpitch (~ 9 nx ny) < 2^31
+  if ((int64_t)p->ny * (int64_t)row_pitch(p->nx) >= (int64_t)1 << 31) return LBM_ERR_INVALID_ARG;
   if (p->model != LBM_MODEL_P && p->model != LBM_MODEL_FE) return LBM_ERR_INVALID_ARG;
   if (p->eos != LBM_EOS_VDW && p->eos != LBM_EOS_CS) return LBM_ERR_INVALID_ARG;
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED) return LBM_ERR_INVALID_ARG;
@@ -931,6 +1064,7 @@ KParams<C> make_kparams(const lbm_params* p, double rho_ref, int nstrips,
   KParams<C> k{};
   k.nx = p->nx;
   k.ny = p->ny;
+  k.rowpitch = (int)row_pitch(p->nx);
   k.nstrips = nstrips;
   k.nseg = nseg;
   k.LY = LY;
@@ -1002,23 +1136,52 @@ struct lbm_ctx {
   int have_prev;
   double rho_ref;  // storage shift reference (0 for FP64)
   int nstrips, nseg, LY, xcd_remap;
+  int pipe;  // 1: software-pipelined step kernel
+  int nt;    // non-temporal population access: bit 0 stores, bit 1 loads
+  int wpe;   // 1: register-capped variant for a higher occupancy
   KParams<double> kd;
   KParams<float> kf;
 };
 
 namespace {
 
-template <int MODEL, int EOS, class S, class C>
-void launch_step(lbm_ctx* c, const KParams<C>& kp) {
+// Occupancy targets (waves per SIMD) of the register-capped variants.
+template <int MODEL, class S>
+constexpr int wpe_target() {
+  return sizeof(S) == 8 ? (MODEL == MODEL_P ? 4 : 3) : (MODEL == MODEL_P ? 8 : 5);
+}
+
+template <int MODEL, int EOS, class S, class C, int NT, int WPE>
+void launch_step_w(lbm_ctx* c, const KParams<C>& kp) {
   const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
   S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
   unsigned* flags = (unsigned*)(c->ws + c->L.flags);
   dim3 grid(c->nstrips * c->nseg), block(kBX);
-  if (MODEL == MODEL_P)
-    hipLaunchKernelGGL((k_step_p<EOS, S, C, kBX>), grid, block, 0, c->stream, src, dst, kp, flags);
+  if (MODEL == MODEL_P && c->pipe)
+    hipLaunchKernelGGL((k_step_p_pipe<EOS, S, C, kBX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+  else if (MODEL == MODEL_P)
+    hipLaunchKernelGGL((k_step_p<EOS, S, C, kBX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
   else
-    hipLaunchKernelGGL((k_step_fe<EOS, S, C, kBX>), grid, block, 0, c->stream, src, dst, kp, flags);
+    hipLaunchKernelGGL((k_step_fe<EOS, S, C, kBX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
   c->cur ^= 1;
+}
+
+template <int MODEL, int EOS, class S, class C, int NT>
+void launch_step_nt(lbm_ctx* c, const KParams<C>& kp) {
+  if (c->wpe)
+    launch_step_w<MODEL, EOS, S, C, NT, wpe_target<MODEL, S>()>(c, kp);
+  else
+    launch_step_w<MODEL, EOS, S, C, NT, 0>(c, kp);
+}
+
+template <int MODEL, int EOS, class S, class C>
+void launch_step(lbm_ctx* c, const KParams<C>& kp) {
+  switch (c->nt) {
+    case 1: launch_step_nt<MODEL, EOS, S, C, 1>(c, kp); break;
+    case 2: launch_step_nt<MODEL, EOS, S, C, 2>(c, kp); break;
+    case 3: launch_step_nt<MODEL, EOS, S, C, 3>(c, kp); break;
+    default: launch_step_nt<MODEL, EOS, S, C, 0>(c, kp); break;
+  }
 }
 
 template <int MODEL, int EOS>
@@ -1050,10 +1213,10 @@ void launch_init(lbm_ctx* c, const double* rho0) {
   size_t N = (size_t)c->p.nx * c->p.ny;
   if (c->p.model == LBM_MODEL_P)
     hipLaunchKernelGGL((k_init<MODEL_P, S>), dim3(grid1d(N)), dim3(256), 0, c->stream,
-                       rho0, dst, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+                       rho0, dst, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg);
   else
     hipLaunchKernelGGL((k_init<MODEL_FE, S>), dim3(grid1d(N)), dim3(256), 0, c->stream,
-                       rho0, dst, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+                       rho0, dst, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg);
 }
 
 template <int MODEL, int EOS, class S>
@@ -1169,9 +1332,15 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
   c->nstrips = (p->nx + kBX - 1) / kBX;
   // Segment height: enough tiles to fill 256 CUs several times over, at
   // least 8 rows so the two halo rows stay a small overhead.
+  // Launch shape defaults (measured on MI355X at 4096^2, see the tuning
+  // notes): non-temporal population stores, register-capped kernels for a
+  // higher occupancy, the pipelined pseudopotential kernel in FP64, row
+  // segments of 32 (FP64) / 16 (FP32) rows.  Each can be overridden by the
+  // LBM_LY, LBM_PIPE, LBM_NT and LBM_WPE environment variables.
+  const bool fp64 = p->precision == LBM_FP64;
   int LY = env_int("LBM_LY", 0);
   if (LY <= 0) {
-    int target_tiles = 2048;
+    int target_tiles = fp64 ? 2048 : 4096;
     int want_seg = std::max(1, target_tiles / c->nstrips);
     LY = std::max(8, (p->ny + want_seg - 1) / want_seg);
     LY = std::min(LY, 64);
@@ -1181,6 +1350,9 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
   c->nseg = (p->ny + LY - 1) / LY;
   int ntiles = c->nstrips * c->nseg;
   c->xcd_remap = (ntiles >= 64 && ntiles % 8 == 0 && env_int("LBM_NO_XCD_REMAP", 0) == 0) ? 1 : 0;
+  c->pipe = env_int("LBM_PIPE", (fp64 && p->model == LBM_MODEL_P) ? 1 : 0);
+  c->nt = env_int("LBM_NT", 1) & 3;
+  c->wpe = env_int("LBM_WPE", 1) ? 1 : 0;
   c->kd = make_kparams<double>(p, c->rho_ref, c->nstrips, c->nseg, LY, c->xcd_remap);
   c->kf = make_kparams<float>(p, c->rho_ref, c->nstrips, c->nseg, LY, c->xcd_remap);
 
@@ -1246,10 +1418,10 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* d_f) {
   const void* src = c->ws + (c->cur ? c->L.fB : c->L.fA);
   if (c->p.precision == LBM_FP64)
     hipLaunchKernelGGL((k_get_pop<double>), dim3(grid1d(N)), dim3(256), 0, c->stream,
-                       (const double*)src, d_f, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+                       (const double*)src, d_f, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg);
   else
     hipLaunchKernelGGL((k_get_pop<float>), dim3(grid1d(N)), dim3(256), 0, c->stream,
-                       (const float*)src, d_f, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+                       (const float*)src, d_f, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg);
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
 }
 
@@ -1259,10 +1431,10 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* d_f) {
   void* dst = c->ws + (c->cur ? c->L.fB : c->L.fA);
   if (c->p.precision == LBM_FP64)
     hipLaunchKernelGGL((k_set_pop<double>), dim3(grid1d(N)), dim3(256), 0, c->stream,
-                       d_f, (double*)dst, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+                       d_f, (double*)dst, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg);
   else
     hipLaunchKernelGGL((k_set_pop<float>), dim3(grid1d(N)), dim3(256), 0, c->stream,
-                       d_f, (float*)dst, c->p.nx, c->p.ny, c->kd.s0, c->kd.sax, c->kd.sdg);
+                       d_f, (float*)dst, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg);
   c->have_prev = 0;
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
 }
