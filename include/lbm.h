@@ -96,7 +96,18 @@ typedef struct {
   double fx, fy;        /* constant body force added to the model force     */
   double rho_ref;       /* FP32_SHIFTED: reference density of the storage
                            shift (<= 0: the smallest initial density)       */
+  /* Launch shape; 0 selects the tuned default (see lbm_autotune).  Results
+     do not depend on these, only the speed does. */
+  int32_t tile_x;       /* columns per workgroup strip: 0, 64 or 256         */
+  int32_t tile_y;       /* rows per workgroup segment: 0 or 1 .. 1024        */
+  int32_t kernel_flags; /* 0, or LBM_KF_SET | any of the LBM_KF_* below      */
+  int32_t reserved1;    /* must be 0                                        */
 } lbm_params;
+
+#define LBM_KF_SET 0x80000000u  /* kernel_flags given explicitly            */
+#define LBM_KF_NT_STORE 1u      /* non-temporal population stores           */
+#define LBM_KF_REGCAP 2u        /* register-capped kernel, higher occupancy */
+#define LBM_KF_PIPELINE 4u      /* software-pipelined row loop (P only)     */
 
 /* Observables of the current state (Eq. 6a-b and Sec. 5.2). */
 typedef struct {
@@ -150,6 +161,58 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const double* d_f);
 
 /* Free the host context (device memory stays with the caller). */
 lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* Time the step kernel for p (its lattice size, model, EOS and precision)
+ * over a list of launch shapes and kernel variants, `steps` steps each, on
+ * a scratch state started from d_rho0, and return the fastest in
+ * best->tile_x / tile_y / kernel_flags (the other fields are copied from p).
+ * Uses d_workspace (lbm_workspace_bytes(p)); synchronises the stream; the
+ * results of a run never depend on the choice, only its speed. */
+lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
+                        const double* d_rho0, void* hip_stream, int32_t steps,
+                        lbm_params* best, double* best_ms_per_step);
+
+/* ---- batches of independent lattices --------------------------------------
+ * A batch advances n independent problems (sizes, models, EOS and
+ * parameters may differ; the precision is common) in lockstep: each time
+ * step is one launch per (model, EOS, strip width) group over a table of all
+ * tiles of all active problems, and runs of steps are captured in a HIP
+ * graph.  Every check_every steps a checking step measures, per problem,
+ * max |u(t) - u(t - check_every)|; a problem retires as converged when that
+ * is below du_tol (or stays below 1e-6 without falling for 5 checks, the
+ * floor of FP32 storage), or as unstable when it raises NONFINITE or
+ * EOS_DOMAIN.  Retired problems keep their state for lbm_batch_observe(). */
+typedef struct lbm_batch lbm_batch;
+
+#define LBM_BATCH_ACTIVE 0
+#define LBM_BATCH_CONVERGED 1
+#define LBM_BATCH_UNSTABLE 2
+#define LBM_BATCH_MAXSTEPS 3
+
+lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, size_t* bytes);
+
+/* p: host array of n problems (common precision); d_rho0: host array of n
+ * device pointers to each problem's initial density (nx*ny doubles). */
+lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const* d_rho0,
+                            void* d_workspace, size_t bytes, void* hip_stream,
+                            lbm_batch** out);
+
+/* Run until every problem has retired or max_steps more steps were taken.
+ * check_every is rounded up to an even number >= 2.  *steps_run (may be
+ * NULL) receives the number of lockstep steps executed.  Synchronises. */
+lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol,
+                         int64_t max_steps, int64_t* steps_run);
+
+/* Per-problem state (LBM_BATCH_*), steps taken, last measured max |du| and
+ * sticky flags; each pointer may be NULL, else points to n elements. */
+lbm_status lbm_batch_state(lbm_batch* b, int32_t* state, int64_t* steps, double* du,
+                           uint32_t* flags);
+
+/* lbm_observe() for problem i of the batch. */
+lbm_status lbm_batch_observe(lbm_batch* b, int32_t i, int32_t cx, int32_t cy, lbm_obs* out,
+                             double* d_rho, double* d_ux, double* d_uy);
+
+lbm_status lbm_batch_destroy(lbm_batch* b);
 
 /* ---- host thermodynamics (no device work) ------------------------------ */
 

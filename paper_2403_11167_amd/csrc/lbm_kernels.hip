@@ -36,6 +36,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -276,7 +277,7 @@ __device__ __forceinline__ void gather(const C* bot, const C* mid, const C* top,
 template <int MODEL, class C>
 __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
                                         C t0, C t1, C t2, C t3,
-                                        const KParams<C>& kp) {
+                                        const KParams<C>& kp, C& ux_out, C& uy_out) {
   // P: t0 = G^2 |S|^2, t1 = Qxx + Qyy, t2 = Qxx - Qyy, t3 = Qxy.
   // FE: t0 = d_x rho, t1 = d_y rho.
   C jx = (g[1] - g[3]) + ((g[5] - g[7]) - (g[6] - g[8]));
@@ -284,6 +285,8 @@ __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
   C inv = C(1) / rho;
   C ux = (jx + C(0.5) * Fx) * inv;  // Eq. 6b
   C uy = (jy + C(0.5) * Fy) * inv;
+  ux_out = ux;
+  uy_out = uy;
 
   C axs = (g[1] + g[2]) + (g[3] + g[4]);
   C dgs = (g[5] + g[6]) + (g[7] + g[8]);
@@ -394,22 +397,64 @@ __device__ __forceinline__ int wrapi(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-// ---- pseudopotential step ---------------------------------------------------
-template <int EOS, class S, class C, int BX, int NT, int WPE>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_step_p(const S* __restrict__ src,
-                                               S* __restrict__ dst,
-                                               const KParams<C> kp,
-                                               unsigned* __restrict__ flags) {
+// ---- per-tile step bodies -------------------------------------------------
+// One workgroup of BX threads updates the tile [x0, x0 + BX) x [y0, y0 + LY)
+// of one lattice (clipped to the lattice).  The single-lattice kernels and
+// the batched kernels differ only in how they find the tile.
+//
+// With CHK = 1 the step also measures convergence: the velocity of Eq. 6b
+// at every node is compared with the one stored at the previous check
+// (ck.uxp / ck.uyp, overwritten), and the workgroup's max |u - u_prev| is
+// folded into *ck.du (the double's bit pattern, atomically maxed: for
+// non-negative doubles the unsigned order is the numeric order).
+template <class C>
+struct ChkOut {
+  C* uxp;
+  C* uyp;
+  unsigned long long* du;
+};
+
+template <int CHK, class C>
+__device__ __forceinline__ void chk_node(const ChkOut<C>& ck, int n, C ux, C uy, C& dmax) {
+  if constexpr (CHK != 0) {
+    C dx = ux - ck.uxp[n], dy = uy - ck.uyp[n];
+    C d = d_sqrt(dx * dx + dy * dy);
+    dmax = (d > dmax || d != d) ? d : dmax;  // keep NaN: it must not look converged
+    ck.uxp[n] = ux;
+    ck.uyp[n] = uy;
+  }
+}
+
+template <int CHK, class C>
+__device__ __forceinline__ void chk_commit(const ChkOut<C>& ck, C dmax, double* s_du) {
+  if constexpr (CHK != 0) {
+    double d = (double)dmax;
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_xor(d, off, 64);
+      d = (o > d || o != o) ? o : d;
+    }
+    if ((threadIdx.x & 63) == 0) s_du[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = s_du[0];
+      for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = (s_du[i] > m || s_du[i] != s_du[i]) ? s_du[i] : m;
+      unsigned long long bits = (m != m) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(m);
+      atomicMax(ck.du, bits);
+    }
+  }
+}
+
+// Pseudopotential step on one tile.
+template <int EOS, class S, class C, int BX, int NT, int CHK>
+__device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict__ dst,
+                                       const KParams<C>& kp, unsigned* __restrict__ flags,
+                                       int x0, int y0, const ChkOut<C>& ck) {
   __shared__ C psi_s[4][BX + 2];
   __shared__ unsigned s_flag;
+  __shared__ double s_du[BX / 64];
   if (threadIdx.x == 0) s_flag = 0u;
   const int nx = kp.nx, ny = kp.ny;
-  const size_t N = (size_t)nx * ny;
-  const int tile = tile_index(kp.xcd_remap);
-  const int strip = tile % kp.nstrips, seg = tile / kp.nstrips;
-  const int x0 = strip * BX;
   const int w = min(BX, nx - x0);
-  const int y0 = seg * kp.LY;
   const int ly = min(kp.LY, ny - y0);
   const int t = threadIdx.x;
   const bool active = t < w;
@@ -426,6 +471,7 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
   const int hj = (t == 0) ? 0 : w + 1;
 
   unsigned fl = 0;
+  C dmax = C(0);
   C gc[9], gn[9];
   C drho_c = C(0), drho_n = C(0);
 
@@ -489,8 +535,10 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
       C qs, qd, qxy;
       q_terms(v, kp.qa, kp.qb, qs, qd, qxy);
       C rho = kp.rho_ref + drho_c;
-      collide<MODEL_P>(gc, drho_c, rho, Fx, Fy, K, qs, qd, qxy, kp);
-      const int off = wrapi(y, ny) * kp.rowpitch + c0;
+      C ux, uy;
+      collide<MODEL_P>(gc, drho_c, rho, Fx, Fy, K, qs, qd, qxy, kp, ux, uy);
+      chk_node<CHK>(ck, y * nx + x, ux, uy, dmax);
+      const int off = y * kp.rowpitch + c0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)gc[i]);
 #pragma unroll
@@ -499,27 +547,22 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
     }
   }
   commit_flags(fl, flags, &s_flag);
+  chk_commit<CHK>(ck, dmax, s_du);
 }
 
 // Software-pipelined variant: the populations of row y+2 (interior and
 // halo columns) are loaded at the top of the iteration that collides row y
 // and only consumed one iteration later, so their memory latency overlaps
 // the psi row, the barrier and the collision in between.
-template <int EOS, class S, class C, int BX, int NT, int WPE>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_step_p_pipe(const S* __restrict__ src,
-                                                    S* __restrict__ dst,
-                                                    const KParams<C> kp,
-                                                    unsigned* __restrict__ flags) {
+template <int EOS, class S, class C, int BX, int NT>
+__device__ __forceinline__ void tile_p_pipe(const S* __restrict__ src, S* __restrict__ dst,
+                                            const KParams<C>& kp, unsigned* __restrict__ flags,
+                                            int x0, int y0) {
   __shared__ C psi_s[4][BX + 2];
   __shared__ unsigned s_flag;
   if (threadIdx.x == 0) s_flag = 0u;
   const int nx = kp.nx, ny = kp.ny;
-  const size_t N = (size_t)nx * ny;
-  const int tile = tile_index(kp.xcd_remap);
-  const int strip = tile % kp.nstrips, seg = tile / kp.nstrips;
-  const int x0 = strip * BX;
   const int w = min(BX, nx - x0);
-  const int y0 = seg * kp.LY;
   const int ly = min(kp.LY, ny - y0);
   const int t = threadIdx.x;
   const bool active = t < w;
@@ -583,8 +626,9 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
       C qs, qd, qxy;
       q_terms(v, kp.qa, kp.qb, qs, qd, qxy);
       C rho = kp.rho_ref + drho_c;
-      collide<MODEL_P>(gc, drho_c, rho, Fx, Fy, K, qs, qd, qxy, kp);
-      const int off = wrapi(y, ny) * kp.rowpitch + c0;
+      C ux, uy;
+      collide<MODEL_P>(gc, drho_c, rho, Fx, Fy, K, qs, qd, qxy, kp, ux, uy);
+      const int off = y * kp.rowpitch + c0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)gc[i]);
     }
@@ -599,23 +643,18 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
   commit_flags(fl, flags, &s_flag);
 }
 
-// ---- free-energy step -------------------------------------------------------
-template <int EOS, class S, class C, int BX, int NT, int WPE>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_step_fe(const S* __restrict__ src,
-                                                S* __restrict__ dst,
-                                                const KParams<C> kp,
-                                                unsigned* __restrict__ flags) {
+// Free-energy step on one tile.
+template <int EOS, class S, class C, int BX, int NT, int CHK>
+__device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict__ dst,
+                                        const KParams<C>& kp, unsigned* __restrict__ flags,
+                                        int x0, int y0, const ChkOut<C>& ck) {
   __shared__ C rho_s[8][BX + 4];
   __shared__ C mu_s[4][BX + 2];
   __shared__ unsigned s_flag;
+  __shared__ double s_du[BX / 64];
   if (threadIdx.x == 0) s_flag = 0u;
   const int nx = kp.nx, ny = kp.ny;
-  const size_t N = (size_t)nx * ny;
-  const int tile = tile_index(kp.xcd_remap);
-  const int strip = tile % kp.nstrips, seg = tile / kp.nstrips;
-  const int x0 = strip * BX;
   const int w = min(BX, nx - x0);
-  const int y0 = seg * kp.LY;
   const int ly = min(kp.LY, ny - y0);
   const int t = threadIdx.x;
   const bool active = t < w;
@@ -636,12 +675,14 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
   const int hmj = (t == 0) ? 0 : w + 1;  // index in mu_s
 
   unsigned fl = 0;
+  C dmax = C(0);
   C g0[9], g1[9], g2[9];
   C d0 = C(0), d1 = C(0), d2 = C(0);
 
   auto rowoff = [&](int y) { return wrapi(y, ny) * kp.rowpitch; };
 
-  // density of row y into ring slot r (and the populations of interior lanes)
+  // density deviation of row y into ring slot r (and the populations of
+  // interior lanes)
   auto load_row = [&](int y, int slot, C g[9], C& dr) {
     const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
     C* row = rho_s[slot & 7];
@@ -705,8 +746,10 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
       C rho = kp.rho_ref + d0;
       C Fx = -rho * gmx + kp.fx;  // F = -rho grad(mu)
       C Fy = -rho * gmy + kp.fy;
-      collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp);
-      const int off = wrapi(y, ny) * kp.rowpitch + c0;
+      C ux, uy;
+      collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
+      chk_node<CHK>(ck, y * nx + x, ux, uy, dmax);
+      const int off = y * kp.rowpitch + c0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)g0[i]);
 #pragma unroll
@@ -716,6 +759,75 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
     }
   }
   commit_flags(fl, flags, &s_flag);
+  chk_commit<CHK>(ck, dmax, s_du);
+}
+
+// ---- single-lattice step kernels --------------------------------------------
+template <int EOS, class S, class C, int BX, int NT, int WPE>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_step_p(const S* __restrict__ src, S* __restrict__ dst, const KParams<C> kp,
+              unsigned* __restrict__ flags) {
+  const int tile = tile_index(kp.xcd_remap);
+  tile_p<EOS, S, C, BX, NT, 0>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
+                               (tile / kp.nstrips) * kp.LY, ChkOut<C>{nullptr, nullptr, nullptr});
+}
+
+template <int EOS, class S, class C, int BX, int NT, int WPE>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_step_p_pipe(const S* __restrict__ src, S* __restrict__ dst, const KParams<C> kp,
+                   unsigned* __restrict__ flags) {
+  const int tile = tile_index(kp.xcd_remap);
+  tile_p_pipe<EOS, S, C, BX, NT>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
+                                 (tile / kp.nstrips) * kp.LY);
+}
+
+template <int EOS, class S, class C, int BX, int NT, int WPE>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_step_fe(const S* __restrict__ src, S* __restrict__ dst, const KParams<C> kp,
+               unsigned* __restrict__ flags) {
+  const int tile = tile_index(kp.xcd_remap);
+  tile_fe<EOS, S, C, BX, NT, 0>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
+                                (tile / kp.nstrips) * kp.LY, ChkOut<C>{nullptr, nullptr, nullptr});
+}
+
+// Occupancy targets (waves per SIMD) of the register-capped variants.
+template <int MODEL, class S>
+constexpr int wpe_target() {
+  return sizeof(S) == 8 ? (MODEL == MODEL_P ? 4 : 3) : (MODEL == MODEL_P ? 8 : 5);
+}
+
+// ---- batched step kernels -----------------------------------------------------
+// One launch covers every tile of every active lattice of one (model, EOS,
+// strip width) group; the tile table names the lattice and the tile origin,
+// the lattice's descriptor its parameters, buffers, flags and check outputs.
+struct BatchTile {
+  int inst, x0, y0, pad;
+};
+
+template <class C>
+struct InstDesc {
+  KParams<C> kp;
+  void* fA;
+  void* fB;
+  C* uxp;
+  C* uyp;
+  unsigned* flags;
+  unsigned long long* du;
+};
+
+template <int MODEL, int EOS, class S, class C, int BX, int NT, int CHK>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(wpe_target<MODEL, S>())))
+void k_batch_step(const BatchTile* __restrict__ tiles, const InstDesc<C>* __restrict__ inst,
+                  int parity) {
+  const BatchTile bt = tiles[blockIdx.x];
+  const InstDesc<C>* d = inst + bt.inst;
+  const S* src = (const S*)(parity ? d->fB : d->fA);
+  S* dst = (S*)(parity ? d->fA : d->fB);
+  const ChkOut<C> ck{d->uxp, d->uyp, d->du};
+  if constexpr (MODEL == MODEL_P)
+    tile_p<EOS, S, C, BX, NT, CHK>(src, dst, d->kp, d->flags, bt.x0, bt.y0, ck);
+  else
+    tile_fe<EOS, S, C, BX, NT, CHK>(src, dst, d->kp, d->flags, bt.x0, bt.y0, ck);
 }
 
 // ---- initial state ------------------------------------------------------------
@@ -996,7 +1108,6 @@ using namespace lbmk;
 
 namespace {
 
-constexpr int kBX = 256;       // threads (= columns) per strip
 constexpr int kObsThreads = 256;
 constexpr int kObsBlocksMax = 2048;
 constexpr size_t kAlign = 256;
@@ -1124,6 +1235,15 @@ int env_int(const char* name, int dflt) {
   return atoi(v);
 }
 
+// Launch shape of one lattice.
+struct LaunchCfg {
+  int bx;    // strip width (threads per workgroup): 64 or 256
+  int ly;    // segment height
+  int nt;    // 1: non-temporal population stores
+  int wpe;   // 1: register-capped kernel variant
+  int pipe;  // 1: pipelined row loop (pseudopotential, FP64)
+};
+
 }  // namespace
 
 struct lbm_ctx {
@@ -1135,53 +1255,106 @@ struct lbm_ctx {
   int64_t step;
   int have_prev;
   double rho_ref;  // storage shift reference (0 for FP64)
-  int nstrips, nseg, LY, xcd_remap;
-  int pipe;  // 1: software-pipelined step kernel
-  int nt;    // non-temporal population access: bit 0 stores, bit 1 loads
-  int wpe;   // 1: register-capped variant for a higher occupancy
+  LaunchCfg lc;
+  int nstrips, nseg, xcd_remap;
   KParams<double> kd;
   KParams<float> kf;
 };
 
 namespace {
 
-// Occupancy targets (waves per SIMD) of the register-capped variants.
-template <int MODEL, class S>
-constexpr int wpe_target() {
-  return sizeof(S) == 8 ? (MODEL == MODEL_P ? 4 : 3) : (MODEL == MODEL_P ? 8 : 5);
+// Launch-shape resolution: explicit fields of lbm_params first, then the
+// LBM_TILE_X / LBM_LY / LBM_NT / LBM_WPE / LBM_PIPE environment overrides
+// (tuning experiments), then defaults measured on MI355X (4096^2 lattices:
+// 256-column strips, non-temporal stores, register-capped kernels, the
+// pipelined pseudopotential kernel in FP64, 32-row segments in FP64 and
+// 16-row segments in FP32; 64-column strips for lattices narrower than 256).
+LaunchCfg resolve_launch(const lbm_params* p) {
+  const bool fp64 = p->precision == LBM_FP64;
+  LaunchCfg lc{};
+  lc.bx = p->tile_x ? p->tile_x : env_int("LBM_TILE_X", p->nx < 256 ? 64 : 256);
+  if (lc.bx != 64) lc.bx = 256;
+  unsigned kf = (unsigned)p->kernel_flags;
+  if (kf & LBM_KF_SET) {
+    lc.nt = (kf & LBM_KF_NT_STORE) ? 1 : 0;
+    lc.wpe = (kf & LBM_KF_REGCAP) ? 1 : 0;
+    lc.pipe = (kf & LBM_KF_PIPELINE) ? 1 : 0;
+  } else {
+    lc.nt = env_int("LBM_NT", 1) ? 1 : 0;
+    lc.wpe = env_int("LBM_WPE", 1) ? 1 : 0;
+    lc.pipe = env_int("LBM_PIPE", fp64 ? 1 : 0) ? 1 : 0;
+  }
+  if (p->model != LBM_MODEL_P) lc.pipe = 0;
+  int nstrips = (p->nx + lc.bx - 1) / lc.bx;
+  int LY = p->tile_y ? p->tile_y : env_int("LBM_LY", 0);
+  if (LY <= 0) {
+    // enough tiles to fill 256 CUs several times over, segments of at
+    // least 8 rows so the two halo rows stay a small overhead
+    int target_tiles = fp64 ? 2048 : 4096;
+    int want_seg = std::max(1, target_tiles / nstrips);
+    LY = std::max(8, (p->ny + want_seg - 1) / want_seg);
+    LY = std::min(LY, fp64 ? 32 : 16);
+  }
+  lc.ly = std::max(1, std::min(LY, p->ny));
+  return lc;
 }
 
-template <int MODEL, int EOS, class S, class C, int NT, int WPE>
+lbm_status validate_launch(const lbm_params* p) {
+  if (p->tile_x != 0 && p->tile_x != 64 && p->tile_x != 256) return LBM_ERR_INVALID_ARG;
+  if (p->tile_y < 0 || p->tile_y > 1024) return LBM_ERR_INVALID_ARG;
+  if (p->kernel_flags != 0 && !((unsigned)p->kernel_flags & LBM_KF_SET)) return LBM_ERR_INVALID_ARG;
+  if (p->reserved1 != 0) return LBM_ERR_INVALID_ARG;
+  return LBM_OK;
+}
+
+void apply_launch(lbm_ctx* c) {
+  c->nstrips = (c->p.nx + c->lc.bx - 1) / c->lc.bx;
+  c->nseg = (c->p.ny + c->lc.ly - 1) / c->lc.ly;
+  int ntiles = c->nstrips * c->nseg;
+  c->xcd_remap = (ntiles >= 64 && ntiles % 8 == 0 && env_int("LBM_NO_XCD_REMAP", 0) == 0) ? 1 : 0;
+  for (KParams<double>* k : {&c->kd}) {
+    k->nstrips = c->nstrips;
+    k->nseg = c->nseg;
+    k->LY = c->lc.ly;
+    k->xcd_remap = c->xcd_remap;
+  }
+  c->kf.nstrips = c->nstrips;
+  c->kf.nseg = c->nseg;
+  c->kf.LY = c->lc.ly;
+  c->kf.xcd_remap = c->xcd_remap;
+}
+
+template <int MODEL, int EOS, class S, class C, int BX, int NT, int WPE>
 void launch_step_w(lbm_ctx* c, const KParams<C>& kp) {
   const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
   S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
   unsigned* flags = (unsigned*)(c->ws + c->L.flags);
-  dim3 grid(c->nstrips * c->nseg), block(kBX);
-  if (MODEL == MODEL_P && c->pipe)
-    hipLaunchKernelGGL((k_step_p_pipe<EOS, S, C, kBX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+  dim3 grid(c->nstrips * c->nseg), block(BX);
+  if (MODEL == MODEL_P && c->lc.pipe && sizeof(C) == 8)
+    hipLaunchKernelGGL((k_step_p_pipe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
   else if (MODEL == MODEL_P)
-    hipLaunchKernelGGL((k_step_p<EOS, S, C, kBX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+    hipLaunchKernelGGL((k_step_p<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
   else
-    hipLaunchKernelGGL((k_step_fe<EOS, S, C, kBX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+    hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
   c->cur ^= 1;
 }
 
-template <int MODEL, int EOS, class S, class C, int NT>
-void launch_step_nt(lbm_ctx* c, const KParams<C>& kp) {
-  if (c->wpe)
-    launch_step_w<MODEL, EOS, S, C, NT, wpe_target<MODEL, S>()>(c, kp);
-  else
-    launch_step_w<MODEL, EOS, S, C, NT, 0>(c, kp);
+template <int MODEL, int EOS, class S, class C, int BX>
+void launch_step_bx(lbm_ctx* c, const KParams<C>& kp) {
+  constexpr int W = wpe_target<MODEL, S>();
+  if (c->lc.nt) {
+    if (c->lc.wpe) launch_step_w<MODEL, EOS, S, C, BX, 1, W>(c, kp);
+    else launch_step_w<MODEL, EOS, S, C, BX, 1, 0>(c, kp);
+  } else {
+    if (c->lc.wpe) launch_step_w<MODEL, EOS, S, C, BX, 0, W>(c, kp);
+    else launch_step_w<MODEL, EOS, S, C, BX, 0, 0>(c, kp);
+  }
 }
 
 template <int MODEL, int EOS, class S, class C>
 void launch_step(lbm_ctx* c, const KParams<C>& kp) {
-  switch (c->nt) {
-    case 1: launch_step_nt<MODEL, EOS, S, C, 1>(c, kp); break;
-    case 2: launch_step_nt<MODEL, EOS, S, C, 2>(c, kp); break;
-    case 3: launch_step_nt<MODEL, EOS, S, C, 3>(c, kp); break;
-    default: launch_step_nt<MODEL, EOS, S, C, 0>(c, kp); break;
-  }
+  if (c->lc.bx == 64) launch_step_bx<MODEL, EOS, S, C, 64>(c, kp);
+  else launch_step_bx<MODEL, EOS, S, C, 256>(c, kp);
 }
 
 template <int MODEL, int EOS>
@@ -1251,62 +1424,25 @@ void observe_dispatch_prec(lbm_ctx* c, int cx, int cy, double* r, double* ux, do
     launch_observe<MODEL, EOS, float>(c, cx, cy, r, ux, uy);
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* lbm_status_string(lbm_status s) {
-  switch (s) {
-    case LBM_OK: return "ok";
-    case LBM_ERR_INVALID_ARG: return "invalid argument";
-    case LBM_ERR_EOS_DOMAIN: return "density outside the equation-of-state domain";
-    case LBM_ERR_UNSUPPORTED: return "unsupported option";
-    case LBM_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
-    case LBM_ERR_HIP: return "HIP runtime error";
-    case LBM_ERR_NO_CONVERGENCE: return "solver did not converge";
-  }
-  return "unknown status";
-}
-
-lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
-  if (!bytes) return LBM_ERR_INVALID_ARG;
-  lbm_status st = validate(p);
-  if (st != LBM_OK) return st;
-  *bytes = make_layout(p).total;
-  return LBM_OK;
-}
-
-lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
-                    const double* d_rho0, void* hip_stream, lbm_ctx** out) {
-  if (!out || !d_rho0) return LBM_ERR_INVALID_ARG;
-  lbm_status st = validate(p);
-  if (st != LBM_OK) return st;
-  Layout L = make_layout(p);
-  if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0)
-    return LBM_ERR_WORKSPACE;
-  hipStream_t stream = (hipStream_t)hip_stream;
+// Context set-up shared by lbm_init and the batch: validation already done,
+// rho0 checked on the host (hrho0), workspace carved.
+lbm_status ctx_setup(const lbm_params* p, void* d_workspace, const double* d_rho0,
+                     const std::vector<double>& hrho0, hipStream_t stream, lbm_ctx** out) {
   size_t N = (size_t)p->nx * p->ny;
-
-  // Host copy of rho0 for the domain check and the FP32 reference density.
-  std::vector<double> h(N);
-  if (hipMemcpyAsync(h.data(), d_rho0, N * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess)
-    return LBM_ERR_HIP;
-  if (hipStreamSynchronize(stream) != hipSuccess) return LBM_ERR_HIP;
   double rmin = INFINITY;
   for (size_t n = 0; n < N; ++n) {
-    double r = h[n];
+    double r = hrho0[n];
     if (!std::isfinite(r)) return LBM_ERR_EOS_DOMAIN;
     double lim = (p->eos == LBM_EOS_CS) ? p->b * r / 4.0 : p->b * r;
     if (!(lim < 1.0) || !(r > 0.0)) return LBM_ERR_EOS_DOMAIN;
     rmin = std::min(rmin, r);
   }
-
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return LBM_ERR_INVALID_ARG;
   c->p = *p;
   c->stream = stream;
   c->ws = (char*)d_workspace;
-  c->L = L;
+  c->L = make_layout(p);
   c->cur = 0;
   c->step = 0;
   c->have_prev = 0;
@@ -1328,35 +1464,11 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
     q = ldexp(m, ex - 20);
     c->rho_ref = 36.0 * q;
   }
-
-  c->nstrips = (p->nx + kBX - 1) / kBX;
-  // Segment height: enough tiles to fill 256 CUs several times over, at
-  // least 8 rows so the two halo rows stay a small overhead.
-  // Launch shape defaults (measured on MI355X at 4096^2, see the tuning
-  // notes): non-temporal population stores, register-capped kernels for a
-  // higher occupancy, the pipelined pseudopotential kernel in FP64, row
-  // segments of 32 (FP64) / 16 (FP32) rows.  Each can be overridden by the
-  // LBM_LY, LBM_PIPE, LBM_NT and LBM_WPE environment variables.
-  const bool fp64 = p->precision == LBM_FP64;
-  int LY = env_int("LBM_LY", 0);
-  if (LY <= 0) {
-    int target_tiles = fp64 ? 2048 : 4096;
-    int want_seg = std::max(1, target_tiles / c->nstrips);
-    LY = std::max(8, (p->ny + want_seg - 1) / want_seg);
-    LY = std::min(LY, 64);
-  }
-  LY = std::min(LY, p->ny);
-  c->LY = LY;
-  c->nseg = (p->ny + LY - 1) / LY;
-  int ntiles = c->nstrips * c->nseg;
-  c->xcd_remap = (ntiles >= 64 && ntiles % 8 == 0 && env_int("LBM_NO_XCD_REMAP", 0) == 0) ? 1 : 0;
-  c->pipe = env_int("LBM_PIPE", (fp64 && p->model == LBM_MODEL_P) ? 1 : 0);
-  c->nt = env_int("LBM_NT", 1) & 3;
-  c->wpe = env_int("LBM_WPE", 1) ? 1 : 0;
-  c->kd = make_kparams<double>(p, c->rho_ref, c->nstrips, c->nseg, LY, c->xcd_remap);
-  c->kf = make_kparams<float>(p, c->rho_ref, c->nstrips, c->nseg, LY, c->xcd_remap);
-
-  if (hipMemsetAsync(c->ws + L.flags, 0, kAlign, stream) != hipSuccess) {
+  c->lc = resolve_launch(p);
+  c->kd = make_kparams<double>(p, c->rho_ref, 1, 1, c->lc.ly, 0);
+  c->kf = make_kparams<float>(p, c->rho_ref, 1, 1, c->lc.ly, 0);
+  apply_launch(c);
+  if (hipMemsetAsync(c->ws + c->L.flags, 0, kAlign, stream) != hipSuccess) {
     delete c;
     return LBM_ERR_HIP;
   }
@@ -1370,17 +1482,16 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
   return LBM_OK;
 }
 
-lbm_status lbm_step(lbm_ctx* c, int64_t n) {
-  if (!c || n < 0) return LBM_ERR_INVALID_ARG;
-  for (int64_t k = 0; k < n; ++k) step_once(c);
-  c->step += n;
-  if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
+lbm_status read_host(const double* d, size_t n, hipStream_t stream, std::vector<double>& h) {
+  h.resize(n);
+  if (hipMemcpyAsync(h.data(), d, n * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return LBM_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return LBM_ERR_HIP;
   return LBM_OK;
 }
 
-lbm_status lbm_observe(lbm_ctx* c, int32_t cx, int32_t cy, lbm_obs* out,
-                       double* d_rho, double* d_ux, double* d_uy) {
-  if (!c || !out) return LBM_ERR_INVALID_ARG;
+lbm_status observe_impl(lbm_ctx* c, int32_t cx, int32_t cy, lbm_obs* out,
+                        double* d_rho, double* d_ux, double* d_uy) {
   if (c->p.model == LBM_MODEL_P) {
     if (c->p.eos == LBM_EOS_CS) observe_dispatch_prec<MODEL_P, EOS_CS>(c, cx, cy, d_rho, d_ux, d_uy);
     else observe_dispatch_prec<MODEL_P, EOS_VDW>(c, cx, cy, d_rho, d_ux, d_uy);
@@ -1410,6 +1521,61 @@ lbm_status lbm_observe(lbm_ctx* c, int32_t cx, int32_t cy, lbm_obs* out,
   out->reserved = 0;
   c->have_prev = 1;
   return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_INVALID_ARG: return "invalid argument";
+    case LBM_ERR_EOS_DOMAIN: return "density outside the equation-of-state domain";
+    case LBM_ERR_UNSUPPORTED: return "unsupported option";
+    case LBM_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case LBM_ERR_HIP: return "HIP runtime error";
+    case LBM_ERR_NO_CONVERGENCE: return "solver did not converge";
+  }
+  return "unknown status";
+}
+
+lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
+  if (!bytes) return LBM_ERR_INVALID_ARG;
+  lbm_status st = validate(p);
+  if (st != LBM_OK) return st;
+  if ((st = validate_launch(p)) != LBM_OK) return st;
+  *bytes = make_layout(p).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
+                    const double* d_rho0, void* hip_stream, lbm_ctx** out) {
+  if (!out || !d_rho0) return LBM_ERR_INVALID_ARG;
+  lbm_status st = validate(p);
+  if (st != LBM_OK) return st;
+  if ((st = validate_launch(p)) != LBM_OK) return st;
+  Layout L = make_layout(p);
+  if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0)
+    return LBM_ERR_WORKSPACE;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  std::vector<double> h;
+  if ((st = read_host(d_rho0, (size_t)p->nx * p->ny, stream, h)) != LBM_OK) return st;
+  return ctx_setup(p, d_workspace, d_rho0, h, stream, out);
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c || n < 0) return LBM_ERR_INVALID_ARG;
+  for (int64_t k = 0; k < n; ++k) step_once(c);
+  c->step += n;
+  if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
+  return LBM_OK;
+}
+
+lbm_status lbm_observe(lbm_ctx* c, int32_t cx, int32_t cy, lbm_obs* out,
+                       double* d_rho, double* d_ux, double* d_uy) {
+  if (!c || !out) return LBM_ERR_INVALID_ARG;
+  return observe_impl(c, cx, cy, out, d_rho, d_ux, d_uy);
 }
 
 lbm_status lbm_get_populations(lbm_ctx* c, double* d_f) {
@@ -1442,6 +1608,473 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* d_f) {
 lbm_status lbm_destroy(lbm_ctx* c) {
   if (!c) return LBM_ERR_INVALID_ARG;
   delete c;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
+                        const double* d_rho0, void* hip_stream, int32_t steps,
+                        lbm_params* best, double* best_ms_per_step) {
+  if (!best || !d_rho0 || steps < 1) return LBM_ERR_INVALID_ARG;
+  lbm_status st = validate(p);
+  if (st != LBM_OK) return st;
+  Layout L = make_layout(p);
+  if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0)
+    return LBM_ERR_WORKSPACE;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  std::vector<double> h;
+  if ((st = read_host(d_rho0, (size_t)p->nx * p->ny, stream, h)) != LBM_OK) return st;
+  const bool fp64 = p->precision == LBM_FP64;
+  std::vector<int> bxs = {64, 256};
+  std::vector<int> lys = {8, 16, 32, 64};
+  std::vector<unsigned> kfs = {LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_REGCAP,
+                               LBM_KF_SET | LBM_KF_NT_STORE,
+                               LBM_KF_SET | LBM_KF_REGCAP};
+  if (fp64 && p->model == LBM_MODEL_P)
+    kfs.push_back(LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_REGCAP | LBM_KF_PIPELINE);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBM_ERR_HIP;
+  double best_t = INFINITY;
+  lbm_params bp = *p;
+  for (int bx : bxs) {
+    if (bx == 256 && p->nx < 192) continue;
+    for (int ly : lys) {
+      if (ly > p->ny) continue;
+      for (unsigned kf : kfs) {
+        lbm_params q = *p;
+        q.tile_x = bx;
+        q.tile_y = ly;
+        q.kernel_flags = (int32_t)kf;
+        lbm_ctx* c = nullptr;
+        if ((st = ctx_setup(&q, d_workspace, d_rho0, h, stream, &c)) != LBM_OK) break;
+        step_once(c);  // warm-up (and first-touch of the second buffer)
+        hipEventRecord(e0, stream);
+        for (int k = 0; k < steps; ++k) step_once(c);
+        hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) st = LBM_ERR_HIP;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        delete c;
+        if (st != LBM_OK) break;
+        double t = ms / steps;
+        if (t < best_t) {
+          best_t = t;
+          bp = q;
+        }
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != LBM_OK) return st;
+  *best = bp;
+  if (best_ms_per_step) *best_ms_per_step = best_t;
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================
+// Batches of independent lattices
+// =============================================================================
+namespace {
+
+struct BatchInst {
+  lbm_ctx* ctx;
+  size_t chk_off;   // per-instance check velocities (2 N values of type C)
+  int state;        // LBM_BATCH_*
+  int64_t steps;
+  double du, best_du;
+  int stall;        // checks without a new best du
+  int checks;
+  uint32_t flags;
+};
+
+struct GroupKey {
+  int model, eos, bx;
+  bool operator<(const GroupKey& o) const {
+    return model != o.model ? model < o.model : eos != o.eos ? eos < o.eos : bx < o.bx;
+  }
+};
+
+}  // namespace
+
+struct lbm_batch {
+  int n;
+  int fp64;
+  hipStream_t stream;      // the caller's stream: graphs are launched on it
+  hipStream_t cap_stream;  // library stream the graphs are captured on
+  hipStream_t launch;      // stream the step launches are issued to
+  char* ws;
+  std::vector<BatchInst> inst;
+  size_t desc_off, tiles_off, du_off, tiles_cap;
+  int parity;  // common population parity of all instances
+  // one tile table per (model, EOS, strip width) group, all in one buffer
+  std::vector<std::pair<GroupKey, std::pair<int, int>>> groups;  // key -> (offset, count)
+  bool tables_valid;
+  hipGraphExec_t graph;
+  int graph_steps;
+  int graph_parity;
+};
+
+namespace {
+
+struct BatchLayout {
+  std::vector<size_t> inst_off, chk_off;
+  size_t desc_off, tiles_off, du_off, total, tiles_cap;
+};
+
+BatchLayout make_batch_layout(int n, const lbm_params* p) {
+  BatchLayout B;
+  size_t off = 0;
+  size_t tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    B.inst_off.push_back(off);
+    off += make_layout(&p[i]).total;
+    size_t N = (size_t)p[i].nx * p[i].ny;
+    size_t es = p[i].precision == LBM_FP64 ? 8 : 4;
+    B.chk_off.push_back(off);
+    off += align_up(2 * N * es);
+    LaunchCfg lc = resolve_launch(&p[i]);
+    tiles += (size_t)((p[i].nx + lc.bx - 1) / lc.bx) * ((p[i].ny + lc.ly - 1) / lc.ly);
+  }
+  size_t desc = std::max(sizeof(InstDesc<double>), sizeof(InstDesc<float>));
+  B.desc_off = off;
+  off += align_up(n * desc);
+  B.tiles_cap = tiles;
+  B.tiles_off = off;
+  off += align_up(tiles * sizeof(BatchTile));
+  B.du_off = off;
+  off += align_up(n * sizeof(unsigned long long));
+  B.total = off;
+  return B;
+}
+
+template <int MODEL, int EOS, class S, class C, int BX>
+void launch_batch_group(lbm_batch* b, const BatchTile* tiles, int ntiles, int chk) {
+  const InstDesc<C>* desc = (const InstDesc<C>*)(b->ws + b->desc_off);
+  if (chk)
+    hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 1>), dim3(ntiles), dim3(BX), 0,
+                       b->launch, tiles, desc, b->parity);
+  else
+    hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 0>), dim3(ntiles), dim3(BX), 0,
+                       b->launch, tiles, desc, b->parity);
+}
+
+template <class S, class C>
+void batch_step_typed(lbm_batch* b, int chk) {
+  const BatchTile* base = (const BatchTile*)(b->ws + b->tiles_off);
+  for (auto& g : b->groups) {
+    const GroupKey& k = g.first;
+    const BatchTile* t = base + g.second.first;
+    int cnt = g.second.second;
+    if (cnt == 0) continue;
+#define LBM_GROUP(M, E, X)                                                       \
+  if (k.model == M && k.eos == E && k.bx == X) launch_batch_group<M, E, S, C, X>(b, t, cnt, chk)
+    LBM_GROUP(MODEL_P, EOS_CS, 64);
+    LBM_GROUP(MODEL_P, EOS_CS, 256);
+    LBM_GROUP(MODEL_P, EOS_VDW, 64);
+    LBM_GROUP(MODEL_P, EOS_VDW, 256);
+    LBM_GROUP(MODEL_FE, EOS_CS, 64);
+    LBM_GROUP(MODEL_FE, EOS_CS, 256);
+    LBM_GROUP(MODEL_FE, EOS_VDW, 64);
+    LBM_GROUP(MODEL_FE, EOS_VDW, 256);
+#undef LBM_GROUP
+  }
+  b->parity ^= 1;
+}
+
+void batch_step(lbm_batch* b, int chk) {
+  if (b->fp64) batch_step_typed<double, double>(b, chk);
+  else batch_step_typed<float, float>(b, chk);
+}
+
+// Rebuild the tile tables of the active instances, largest first within
+// each group, and upload them (outside any graph capture).
+lbm_status rebuild_tables(lbm_batch* b) {
+  std::map<GroupKey, std::vector<BatchTile>> tabs;
+  std::vector<int> order(b->n);
+  for (int i = 0; i < b->n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int c) {
+    const lbm_params& pa = b->inst[a].ctx->p;
+    const lbm_params& pc = b->inst[c].ctx->p;
+    return (int64_t)pa.nx * pa.ny > (int64_t)pc.nx * pc.ny;
+  });
+  for (int i : order) {
+    BatchInst& I = b->inst[i];
+    if (I.state != LBM_BATCH_ACTIVE) continue;
+    lbm_ctx* c = I.ctx;
+    GroupKey key{c->p.model, c->p.eos, c->lc.bx};
+    auto& v = tabs[key];
+    for (int s = 0; s < c->nseg; ++s)
+      for (int x = 0; x < c->nstrips; ++x) v.push_back(BatchTile{i, x * c->lc.bx, s * c->lc.ly, 0});
+  }
+  std::vector<BatchTile> all;
+  b->groups.clear();
+  for (auto& kv : tabs) {
+    b->groups.push_back({kv.first, {(int)all.size(), (int)kv.second.size()}});
+    all.insert(all.end(), kv.second.begin(), kv.second.end());
+  }
+  if (all.size() > b->tiles_cap) return LBM_ERR_WORKSPACE;
+  if (!all.empty() &&
+      hipMemcpyAsync(b->ws + b->tiles_off, all.data(), all.size() * sizeof(BatchTile),
+                     hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    return LBM_ERR_HIP;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_ERR_HIP;
+  b->tables_valid = true;
+  return LBM_OK;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+void drop_graph(lbm_batch* b) {
+  if (b->graph) hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_steps = 0;
+}
+
+// Capture `steps` lockstep steps (the last one checking) as one graph.  The
+// capture runs on the library's own stream (the caller's stream may be the
+// null stream, which cannot be captured); the graph is launched on the
+// caller's stream.  The du slots are cleared by a kernel, not a memset node.
+lbm_status capture_chunk(lbm_batch* b, int steps) {
+  drop_graph(b);
+  int parity0 = b->parity;
+  hipGraph_t g;
+  if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return LBM_ERR_HIP;
+  b->launch = b->cap_stream;
+  for (int s = 0; s < steps - 1; ++s) batch_step(b, 0);
+  hipLaunchKernelGGL(k_zero_u64, dim3((b->n + 255) / 256), dim3(256), 0, b->cap_stream,
+                     (unsigned long long*)(b->ws + b->du_off), b->n);
+  batch_step(b, 1);
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  b->launch = b->stream;
+  b->parity = parity0;  // capture only recorded the launches
+  if (e != hipSuccess) return LBM_ERR_HIP;
+  e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->graph = nullptr;
+    return LBM_ERR_HIP;
+  }
+  b->graph_steps = steps;
+  b->graph_parity = parity0;
+  return LBM_OK;
+}
+
+template <class C>
+InstDesc<C> make_desc(lbm_batch* b, const BatchInst& I) {
+  InstDesc<C> d{};
+  lbm_ctx* c = I.ctx;
+  if constexpr (sizeof(C) == 8) d.kp = c->kd; else d.kp = c->kf;
+  d.fA = c->ws + c->L.fA;
+  d.fB = c->ws + c->L.fB;
+  size_t N = (size_t)c->p.nx * c->p.ny;
+  d.uxp = (C*)(b->ws + I.chk_off);
+  d.uyp = d.uxp + N;
+  d.flags = (unsigned*)(c->ws + c->L.flags);
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, size_t* bytes) {
+  if (n < 1 || !p || !bytes) return LBM_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    lbm_status st = validate(&p[i]);
+    if (st != LBM_OK) return st;
+    if ((st = validate_launch(&p[i])) != LBM_OK) return st;
+    if (p[i].precision != p[0].precision) return LBM_ERR_INVALID_ARG;
+  }
+  *bytes = make_batch_layout(n, p).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const* d_rho0,
+                            void* d_workspace, size_t bytes, void* hip_stream,
+                            lbm_batch** out) {
+  if (!out || !d_rho0) return LBM_ERR_INVALID_ARG;
+  size_t need;
+  lbm_status st = lbm_batch_workspace_bytes(n, p, &need);
+  if (st != LBM_OK) return st;
+  if (!d_workspace || bytes < need || ((uintptr_t)d_workspace % kAlign) != 0)
+    return LBM_ERR_WORKSPACE;
+  for (int i = 0; i < n; ++i)
+    if (!d_rho0[i]) return LBM_ERR_INVALID_ARG;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  BatchLayout B = make_batch_layout(n, p);
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_ERR_INVALID_ARG;
+  b->n = n;
+  b->fp64 = p[0].precision == LBM_FP64;
+  b->stream = stream;
+  b->launch = stream;
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return LBM_ERR_HIP;
+  }
+  b->ws = (char*)d_workspace;
+  b->desc_off = B.desc_off;
+  b->tiles_off = B.tiles_off;
+  b->du_off = B.du_off;
+  b->tiles_cap = B.tiles_cap;
+  b->parity = 0;
+  b->tables_valid = false;
+  b->graph = nullptr;
+  b->graph_steps = 0;
+  b->inst.resize(n);
+  std::vector<double> h;
+  for (int i = 0; i < n && st == LBM_OK; ++i) {
+    BatchInst& I = b->inst[i];
+    I = BatchInst{nullptr, B.chk_off[i], LBM_BATCH_ACTIVE, 0, INFINITY, INFINITY, 0, 0, 0u};
+    st = read_host(d_rho0[i], (size_t)p[i].nx * p[i].ny, stream, h);
+    if (st == LBM_OK) st = ctx_setup(&p[i], b->ws + B.inst_off[i], d_rho0[i], h, stream, &I.ctx);
+  }
+  if (st != LBM_OK) {
+    for (auto& I : b->inst) delete I.ctx;
+    hipStreamDestroy(b->cap_stream);
+    delete b;
+    return st;
+  }
+  // instance descriptors
+  size_t dsz = b->fp64 ? sizeof(InstDesc<double>) : sizeof(InstDesc<float>);
+  std::vector<char> descs(n * dsz);
+  for (int i = 0; i < n; ++i) {
+    if (b->fp64) {
+      InstDesc<double> d = make_desc<double>(b, b->inst[i]);
+      d.du = (unsigned long long*)(b->ws + b->du_off) + i;
+      memcpy(&descs[i * dsz], &d, dsz);
+    } else {
+      InstDesc<float> d = make_desc<float>(b, b->inst[i]);
+      d.du = (unsigned long long*)(b->ws + b->du_off) + i;
+      memcpy(&descs[i * dsz], &d, dsz);
+    }
+  }
+  if (hipMemcpyAsync(b->ws + b->desc_off, descs.data(), descs.size(), hipMemcpyHostToDevice,
+                     stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    for (auto& I : b->inst) delete I.ctx;
+    hipStreamDestroy(b->cap_stream);
+    delete b;
+    return LBM_ERR_HIP;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64_t max_steps,
+                         int64_t* steps_run) {
+  if (!b || check_every < 1 || max_steps < 0 || !(du_tol >= 0)) return LBM_ERR_INVALID_ARG;
+  int K = check_every + (check_every & 1);
+  if (K < 2) K = 2;
+  int64_t done = 0;
+  std::vector<unsigned long long> du_bits(b->n);
+  std::vector<uint32_t> fl(b->n);
+  lbm_status st = LBM_OK;
+  while (done < max_steps) {
+    bool any = false;
+    for (auto& I : b->inst) any |= (I.state == LBM_BATCH_ACTIVE);
+    if (!any) break;
+    if (!b->tables_valid) {
+      if ((st = rebuild_tables(b)) != LBM_OK) break;
+      drop_graph(b);
+    }
+    int chunk = (int)std::min<int64_t>(K, max_steps - done);
+    chunk = std::max(2, chunk - (chunk & 1));
+    if (!b->graph || b->graph_steps != chunk || b->graph_parity != b->parity)
+      if ((st = capture_chunk(b, chunk)) != LBM_OK) break;
+    if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
+    b->parity ^= (chunk & 1);
+    done += chunk;
+    if (hipMemcpyAsync(du_bits.data(), b->ws + b->du_off, b->n * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
+    for (int i = 0; i < b->n; ++i) {
+      lbm_ctx* c = b->inst[i].ctx;
+      if (b->inst[i].state != LBM_BATCH_ACTIVE) continue;
+      if (hipMemcpyAsync(&fl[i], c->ws + c->L.flags, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
+    }
+    if (st != LBM_OK) break;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
+    for (int i = 0; i < b->n; ++i) {
+      BatchInst& I = b->inst[i];
+      if (I.state != LBM_BATCH_ACTIVE) continue;
+      I.steps += chunk;
+      I.ctx->step = I.steps;
+      I.ctx->cur = b->parity;
+      double du;
+      memcpy(&du, &du_bits[i], sizeof(du));
+      I.flags = fl[i];
+      I.checks += 1;
+      if (I.flags & (LBM_FLAG_NONFINITE | LBM_FLAG_EOS_DOMAIN)) {
+        I.state = LBM_BATCH_UNSTABLE;
+        b->tables_valid = false;
+        continue;
+      }
+      if (I.checks == 1) continue;  // the first check only stores u
+      I.du = du;
+      if (du < I.best_du) {
+        I.best_du = du;
+        I.stall = 0;
+      } else {
+        I.stall += 1;
+      }
+      bool conv = du < du_tol || (I.best_du < 1e-6 && I.stall >= 5);
+      if (conv) {
+        I.state = LBM_BATCH_CONVERGED;
+        b->tables_valid = false;
+      }
+    }
+  }
+  if (st == LBM_OK) {
+    // chunks have an even number of steps, so every instance (also one
+    // retired at an earlier check) holds its state in the parity-0 buffer
+    for (auto& I : b->inst) {
+      I.ctx->cur = b->parity;
+      I.ctx->have_prev = 0;
+    }
+    bool any = false;
+    for (auto& I : b->inst) any |= (I.state == LBM_BATCH_ACTIVE);
+    if (any && done >= max_steps)
+      for (auto& I : b->inst)
+        if (I.state == LBM_BATCH_ACTIVE) I.state = LBM_BATCH_MAXSTEPS;
+  }
+  if (steps_run) *steps_run = done;
+  return st;
+}
+
+lbm_status lbm_batch_state(lbm_batch* b, int32_t* state, int64_t* steps, double* du,
+                           uint32_t* flags) {
+  if (!b) return LBM_ERR_INVALID_ARG;
+  for (int i = 0; i < b->n; ++i) {
+    const BatchInst& I = b->inst[i];
+    if (state) state[i] = I.state;
+    if (steps) steps[i] = I.steps;
+    if (du) du[i] = I.du;
+    if (flags) flags[i] = I.flags;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_observe(lbm_batch* b, int32_t i, int32_t cx, int32_t cy, lbm_obs* out,
+                             double* d_rho, double* d_ux, double* d_uy) {
+  if (!b || i < 0 || i >= b->n || !out) return LBM_ERR_INVALID_ARG;
+  lbm_ctx* c = b->inst[i].ctx;
+  // a retired instance stopped at its own parity; active ones share b->parity
+  return observe_impl(c, cx, cy, out, d_rho, d_ux, d_uy);
+}
+
+lbm_status lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_ERR_INVALID_ARG;
+  drop_graph(b);
+  for (auto& I : b->inst) delete I.ctx;
+  hipStreamDestroy(b->cap_stream);
+  delete b;
   return LBM_OK;
 }
 

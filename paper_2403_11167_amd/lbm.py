@@ -22,11 +22,16 @@ EOS_VDW, EOS_CS = 0, 1
 FP64, FP32_SHIFTED = 0, 1
 FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
 
+BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS = 0, 1, 2, 3
+KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE = 0x80000000, 1, 2, 4
+
 EXPORTED_SYMBOLS = [
     "lbm_status_string", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe",
-    "lbm_get_populations", "lbm_set_populations", "lbm_destroy",
+    "lbm_get_populations", "lbm_set_populations", "lbm_destroy", "lbm_autotune",
     "lbm_eos_critical", "lbm_maxwell", "lbm_sigma_li_theory", "lbm_fe_planar_theory",
     "lbm_match_p_to_fe",
+    "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_state",
+    "lbm_batch_observe", "lbm_batch_destroy",
 ]
 
 
@@ -46,7 +51,9 @@ class Params(ctypes.Structure):
                 ("sigma_li", ctypes.c_double), ("kappa_li", ctypes.c_double),
                 ("kappa_p", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("A", ctypes.c_double), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
-                ("rho_ref", ctypes.c_double)]
+                ("rho_ref", ctypes.c_double),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("kernel_flags", ctypes.c_uint32), ("reserved1", ctypes.c_int32)]
 
 
 class Obs(ctypes.Structure):
@@ -90,6 +97,18 @@ def lib():
         L.lbm_sigma_li_theory.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 4 + [D] * 2
         L.lbm_fe_planar_theory.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 5 + [D] * 2
         L.lbm_match_p_to_fe.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 6 + [D] * 3
+        L.lbm_autotune.argtypes = [P, vp, sz, vp, vp, ctypes.c_int32, P, D]
+        L.lbm_batch_workspace_bytes.argtypes = [ctypes.c_int32, P, ctypes.POINTER(sz)]
+        L.lbm_batch_create.argtypes = [ctypes.c_int32, P, ctypes.POINTER(vp), vp, sz, vp,
+                                       ctypes.POINTER(vp)]
+        L.lbm_batch_run.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_int64)]
+        L.lbm_batch_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int64), D,
+                                      ctypes.POINTER(ctypes.c_uint32)]
+        L.lbm_batch_observe.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(Obs), vp, vp, vp]
+        L.lbm_batch_destroy.argtypes = [vp]
         for name in EXPORTED_SYMBOLS:
             if name != "lbm_status_string":
                 getattr(L, name).restype = ctypes.c_int
@@ -167,6 +186,9 @@ class Config:
     fy: float = 0.0
     precision: int = FP64
     rho_ref: float = 0.0
+    tile_x: int = 0
+    tile_y: int = 0
+    kernel_flags: int = 0
 
     def c_params(self) -> Params:
         p = Params()
@@ -177,7 +199,13 @@ class Config:
             p.tau[i] = float(t)
         p.sigma_li, p.kappa_li, p.kappa_p = self.sigma_li, self.kappa_li, self.kappa_p
         p.kappa, p.A, p.fx, p.fy, p.rho_ref = self.kappa, self.A, self.fx, self.fy, self.rho_ref
+        p.tile_x, p.tile_y, p.kernel_flags, p.reserved1 = (self.tile_x, self.tile_y,
+                                                           self.kernel_flags, 0)
         return p
+
+    def with_launch(self, tile_x: int, tile_y: int, kernel_flags: int) -> "Config":
+        import dataclasses
+        return dataclasses.replace(self, tile_x=tile_x, tile_y=tile_y, kernel_flags=kernel_flags)
 
 
 def workspace_bytes(cfg: Config) -> int:
@@ -249,6 +277,93 @@ class Simulation:
         if getattr(self, "_ctx", None) is not None:
             lib().lbm_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(cfg: Config, rho0, steps: int = 20, stream=None):
+    """Fastest launch shape for cfg (see lbm_autotune): (Config, ms/step)."""
+    import torch
+    stream = stream if stream is not None else torch.cuda.current_stream(rho0.device)
+    nbytes = workspace_bytes(cfg)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=rho0.device)
+    p = cfg.c_params()
+    best = Params()
+    ms = ctypes.c_double()
+    _check(lib().lbm_autotune(ctypes.byref(p), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                              ctypes.c_void_p(rho0.data_ptr()), ctypes.c_void_p(stream.cuda_stream),
+                              int(steps), ctypes.byref(best), ctypes.byref(ms)), "lbm_autotune")
+    return cfg.with_launch(best.tile_x, best.tile_y, best.kernel_flags), ms.value
+
+
+class Batch:
+    """Independent lattices advanced in lockstep until each converges or
+    turns unstable (see lbm_batch_run).  rho0s: list of float64 (ny, nx)
+    device tensors, one per Config."""
+
+    def __init__(self, cfgs, rho0s, stream=None):
+        import torch
+        assert len(cfgs) == len(rho0s) and len(cfgs) > 0
+        self.cfgs = list(cfgs)
+        self.n = len(cfgs)
+        dev = rho0s[0].device
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._p = (Params * self.n)(*[c.c_params() for c in cfgs])
+        nbytes = ctypes.c_size_t()
+        _check(lib().lbm_batch_workspace_bytes(self.n, self._p, ctypes.byref(nbytes)),
+               "lbm_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        for c, r in zip(cfgs, rho0s):
+            assert r.dtype == torch.float64 and r.is_contiguous() and tuple(r.shape) == (c.ny, c.nx)
+        self._rho0 = list(rho0s)
+        ptrs = (ctypes.c_void_p * self.n)(*[r.data_ptr() for r in rho0s])
+        h = ctypes.c_void_p()
+        _check(lib().lbm_batch_create(self.n, self._p, ptrs,
+                                      ctypes.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "lbm_batch_create")
+        self._h = h
+
+    def run(self, check_every: int = 100, du_tol: float = 1e-9, max_steps: int = 200000) -> int:
+        done = ctypes.c_int64()
+        _check(lib().lbm_batch_run(self._h, int(check_every), float(du_tol), int(max_steps),
+                                   ctypes.byref(done)), "lbm_batch_run")
+        return done.value
+
+    def state(self):
+        """(state, steps, du, flags) lists."""
+        n = self.n
+        st = (ctypes.c_int32 * n)()
+        steps = (ctypes.c_int64 * n)()
+        du = (ctypes.c_double * n)()
+        fl = (ctypes.c_uint32 * n)()
+        _check(lib().lbm_batch_state(self._h, st, steps, du, fl), "lbm_batch_state")
+        return list(st), list(steps), list(du), list(fl)
+
+    def observe(self, i: int, cx: int = 0, cy: int = 0, fields: bool = False):
+        import torch
+        o = Obs()
+        rho = ux = uy = None
+        if fields:
+            c = self.cfgs[i]
+            rho = torch.empty((c.ny, c.nx), dtype=torch.float64, device=self.device)
+            ux = torch.empty_like(rho)
+            uy = torch.empty_like(rho)
+        ptr = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None)
+        _check(lib().lbm_batch_observe(self._h, int(i), int(cx), int(cy), ctypes.byref(o),
+                                       ptr(rho), ptr(ux), ptr(uy)), "lbm_batch_observe")
+        d = o.as_dict()
+        return (d, (rho, ux, uy)) if fields else d
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().lbm_batch_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

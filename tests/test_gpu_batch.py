@@ -1,0 +1,157 @@
+"""Batched lattices and the autotuner, through the C ABI, against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import theory as th
+from paper_2403_11167_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+FP64_RTOL = 1e-10
+
+
+def dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+def cs_T(a, Tr):
+    return Tr * th.critical(th.CS, a, 4.0, 1.0)[0]
+
+
+def oparams(c: lbm.Config):
+    return oracle.OracleParams(c.nx, c.ny, c.model, c.eos, c.a, c.b, c.R, c.T, tau=list(c.tau),
+                               sigma_li=c.sigma_li, kappa_li=c.kappa_li, kappa_p=c.kappa_p,
+                               kappa=c.kappa, fx=c.fx, fy=c.fy)
+
+
+def oracle_rho(c, rho0, steps):
+    s = oracle.Simulation(oparams(c), rho0)
+    s.step(steps)
+    return s.fields()[0], s.flags
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def mixed_cases(precision=lbm.FP64):
+    """Problems of different sizes, models and EOS (all stable for a while)."""
+    cases = []
+    a = 0.25
+    T = cs_T(a, 0.8)
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    tauP = [1.0] * 9
+    tauP[4] = tauP[6] = 1 / 1.99
+    tauF = [1.0] * 9
+    tauF[1] = 0.75
+    for (nx, ny, model, geo) in [(64, 64, 0, "drop"), (100, 70, 1, "drop"), (257, 33, 0, "flat"),
+                                 (128, 128, 1, "flat"), (300, 90, 0, "drop"), (64, 64, 1, "drop")]:
+        if model == 0:
+            c = lbm.Config(nx, ny, 0, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tauP, sigma_li=0.11,
+                           kappa_p=0.9, kappa_li=-0.5, precision=precision)
+        else:
+            c = lbm.Config(nx, ny, 1, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tauF, kappa=0.5,
+                           precision=precision)
+        r0 = (inputs.droplet(nx, ny, rl, rv, radius=min(nx, ny) / 4) if geo == "drop"
+              else inputs.planar_slab(nx, ny, rl, rv))
+        cases.append((c, r0))
+    # a van der Waals pseudopotential problem (psi real at Tr = 0.9)
+    Tv = 0.9 * 4 / 7
+    rlv, rvv, _ = th.maxwell(th.VDW, 9 / 49, 2 / 21, 1.0, Tv)
+    c = lbm.Config(96, 40, 0, lbm.EOS_VDW, 9 / 49, 2 / 21, 1.0, Tv, precision=precision)
+    cases.append((c, inputs.planar_slab(96, 40, rlv, rvv)))
+    return cases
+
+
+def test_batch_lockstep_matches_oracle():
+    cases = mixed_cases()
+    b = lbm.Batch([c for c, _ in cases], [to_dev(r) for _, r in cases])
+    steps = 120
+    done = b.run(check_every=40, du_tol=0.0, max_steps=steps)
+    assert done == steps
+    st, nsteps, du, fl = b.state()
+    assert all(s == lbm.BATCH_MAXSTEPS for s in st)
+    assert all(n == steps for n in nsteps)
+    for i, (c, r0) in enumerate(cases):
+        obs, (rho, _, _) = b.observe(i, fields=True)
+        rref, fref = oracle_rho(c, r0, steps)
+        assert rel(rho.cpu().numpy(), rref) < FP64_RTOL, i
+        assert obs["flags"] == fref
+        assert obs["step"] == steps
+    b.close()
+
+
+def test_batch_fp32_lockstep_within_fp32_bound():
+    cases = mixed_cases(lbm.FP32_SHIFTED)[:4]
+    b = lbm.Batch([c for c, _ in cases], [to_dev(r) for _, r in cases])
+    steps = 100
+    b.run(check_every=50, du_tol=0.0, max_steps=steps)
+    for i, (c, r0) in enumerate(cases):
+        _, (rho, _, _) = b.observe(i, fields=True)
+        rref, _ = oracle_rho(c, r0, steps)
+        bound = 4.0 * math.sqrt(steps) * 2.0 ** -24 * float(rref.max() / rref.min())
+        assert rel(rho.cpu().numpy(), rref) < bound, i
+    b.close()
+
+
+def test_batch_convergence_and_retirement():
+    """Planar problems converge (max |du| over a check interval below the
+    tolerance) and retire; an unstable free-energy van der Waals problem
+    retires as unstable without disturbing the others.  Each retired
+    problem's state equals the oracle after the same number of steps."""
+    a = 0.5
+    T = cs_T(a, 0.7)
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    _, sig = th.epsilon_li(th.CS, a, 4.0, 1.0, T)
+    tauP = [1.0] * 9
+    tauP[4] = tauP[6] = 1 / 1.99
+    cfgs = [lbm.Config(100, 4, 1, lbm.EOS_CS, a, 4.0, 1.0, T, kappa=0.5),
+            lbm.Config(64, 8, 0, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tauP, sigma_li=sig),
+            lbm.Config(80, 6, 0, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tauP, sigma_li=sig, kappa_p=0.7)]
+    r0s = [inputs.planar_slab(c.nx, c.ny, rl, rv) for c in cfgs]
+    Tv = 0.7 * 4 / 7
+    rlv, rvv, _ = th.maxwell(th.VDW, 9 / 49, 2 / 21, 1.0, Tv)
+    cfgs.append(lbm.Config(64, 64, 1, lbm.EOS_VDW, 9 / 49, 2 / 21, 1.0, Tv, kappa=0.5))
+    r0s.append(inputs.spinodal(64, 64, 0.5 * (rlv + rvv), 0.01, seed=3))
+    b = lbm.Batch(cfgs, [to_dev(r) for r in r0s])
+    b.run(check_every=200, du_tol=1e-12, max_steps=60000)
+    st, nsteps, du, fl = b.state()
+    assert st[:3] == [lbm.BATCH_CONVERGED] * 3, (st, du)
+    assert st[3] == lbm.BATCH_UNSTABLE and fl[3] & (lbm.FLAG_NONFINITE | lbm.FLAG_EOS_DOMAIN)
+    for i in range(3):
+        assert du[i] < 1e-12
+        _, (rho, _, _) = b.observe(i, fields=True)
+        rref, _ = oracle_rho(cfgs[i], r0s[i], nsteps[i])
+        rho = rho.cpu().numpy()
+        assert np.max(np.abs(rho - rref)) / rref.max() < FP64_RTOL
+    b.close()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_autotuned_launch_keeps_parity(model):
+    a = 0.25
+    T = cs_T(a, 0.8)
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    if model == 0:
+        cfg = lbm.Config(320, 200, 0, lbm.EOS_CS, a, 4.0, 1.0, T, sigma_li=0.1, kappa_p=0.8)
+    else:
+        tau = [1.0] * 9
+        tau[1] = 0.75
+        cfg = lbm.Config(320, 200, 1, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tau, kappa=0.5)
+    r0 = inputs.droplet(320, 200, rl, rv, radius=40.0)
+    tuned, ms = lbm.autotune(cfg, to_dev(r0), steps=5)
+    assert tuned.tile_x in (64, 256) and tuned.tile_y >= 1 and ms > 0
+    sim = lbm.Simulation(tuned, to_dev(r0))
+    sim.step(60)
+    _, (rho, _, _) = sim.observe(fields=True)
+    rref, _ = oracle_rho(cfg, r0, 60)
+    assert rel(rho.cpu().numpy(), rref) < FP64_RTOL
