@@ -128,18 +128,24 @@ def cpu_baseline(cfg_factory, rho0, target_seconds: float):
                        f"initial state ({total_t:.1f} s)")
 
 
-def load_traffic(kernel: str):
+def load_traffic(variant: str):
+    """(HBM bytes per launch from the committed counter runs, kernel name);
+    bytes are None unless the counters were taken on the current kernel
+    source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     try:
         d = json.load(open(path))
-    except Exception:
-        return None
+    except (OSError, ValueError):
+        return None, None
+    k = d.get("kernels", {}).get(variant)
+    if k is None:
+        return None, None
+    name = k.get("name")
     if d.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+        return None, name
+    return k.get("bytes_per_launch"), name
 
 
 def main():
@@ -203,14 +209,14 @@ def main():
     ms_per_step = t_p + t_fe
     value = 2 * N / (ms_per_step * 1e-3) / 1e6
 
-    dom = "P" if t_p >= t_fe else "FE"
+    dom = "P_fp64" if t_p >= t_fe else "FE_fp64"
     dom_ms = max(t_p, t_fe)
-    kernel_name = "k_step_p<double>" if dom == "P" else "k_step_fe<double>"
     algo_bytes = 18 * 8 * N  # 9 population reads + 9 writes, FP64
     achieved = algo_bytes / (dom_ms * 1e-3) / 1e9
+    traffic, kname = load_traffic(dom)
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=load_traffic(kernel_name),
-                    kernel=kernel_name, algorithmic_bytes_per_launch=algo_bytes,
+                    frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                    kernel=kname or dom, variant=dom, algorithmic_bytes_per_launch=algo_bytes,
                     launch_ms=dom_ms)
 
     cpu = None
