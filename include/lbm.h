@@ -203,6 +203,15 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
 lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol,
                          int64_t max_steps, int64_t* steps_run);
 
+/* Step limit of problem i (total steps since creation; default INT64_MAX).
+ * An active problem retires with LBM_BATCH_MAXSTEPS at the first check at
+ * which its step count has reached the limit, so it may overshoot by up to
+ * check_every - 1 steps; one already at or past the limit retires at once.
+ * A problem in state LBM_BATCH_MAXSTEPS whose step count is below the new
+ * limit becomes active again and continues from its current state at the
+ * next lbm_batch_run().  Host-only; no device work. */
+lbm_status lbm_batch_set_limit(lbm_batch* b, int32_t i, int64_t max_steps);
+
 /* Per-problem state (LBM_BATCH_*), steps taken, last measured max |du| and
  * sticky flags; each pointer may be NULL, else points to n elements. */
 lbm_status lbm_batch_state(lbm_batch* b, int32_t* state, int64_t* steps, double* du,
@@ -250,6 +259,66 @@ lbm_status lbm_match_p_to_fe(int32_t eos, double a, double b, double R,
                              double T, double kappa_fe, double target_width,
                              double* sigma_li, double* kappa_p,
                              double* kappa_li);
+
+/* ---- calibration surrogate --------------------------------------------------
+ * The paper fixes the pseudopotential parameters by preliminary simulations
+ * at each temperature (Sec. 3 and 5.1-5.2).  The surrogate replaces that
+ * search by a multilayer perceptron 4 -> 128 -> 128 -> 128 -> 4 (GELU after
+ * each hidden layer) mapping a calibration tuple x = (model, Tr, width
+ * parameter w, kappa) to y = (rho_l, rho_v, sigma, W) as measured by
+ * equilibrium runs of this library, and seeds near-equilibrium initial
+ * profiles for new runs.
+ *
+ * Parameters: LBM_MLP_NPARAMS floats in device memory, per layer the n_in x
+ * n_out weights input-major (W[k][j] at k * n_out + j) followed by the n_out
+ * biases; layers 4x128, 128x128, 128x128, 128x4.  Normalisation: network
+ * input (x - x_shift) * x_scale; network output o gives y = exp(o * y_scale
+ * + y_shift); the loss is the mean over samples and outputs of
+ * (o - (log y - y_shift) / y_scale)^2.  Feature and target arrays are
+ * row-major n x 4 floats; targets must be positive.  Flag LBM_MLP_BF16
+ * rounds every product operand (layer inputs, weights) to bfloat16 and
+ * accumulates in FP32; 0 computes in FP32.  All calls are asynchronous on
+ * hip_stream; the caller owns every buffer. */
+#define LBM_MLP_NPARAMS 34180
+#define LBM_MLP_BF16 1
+
+typedef struct {
+  float x_shift[4], x_scale[4];
+  float y_shift[4], y_scale[4];  /* y_scale != 0 */
+} lbm_mlp_norm;
+
+/* Predictions y (n x 4) for features x (n x 4); n == 0 is a no-op. */
+lbm_status lbm_mlp_forward(const float* d_params, const lbm_mlp_norm* norm, const float* d_x,
+                           int32_t n, float* d_y, int32_t flags, void* hip_stream);
+
+/* Workspace for a gradient over n samples (about n / 16 * 137 KB, at most
+ * 17.5 MB), 256-byte aligned. */
+lbm_status lbm_mlp_workspace_bytes(int32_t n, size_t* bytes);
+
+/* Loss and gradient (LBM_MLP_NPARAMS floats, overwritten) over n samples of
+ * a data set of n_rows rows: sample s is row d_idx[s] (d_idx may be NULL:
+ * rows 0..n-1).  A row index outside [0, n_rows) makes *d_loss NaN and the
+ * sample contributes nothing.  d_loss (one float) may be NULL.  The
+ * gradient is summed per workgroup and then in a fixed order, so repeated
+ * calls give identical results. */
+lbm_status lbm_mlp_grad(const float* d_params, const lbm_mlp_norm* norm, const float* d_x,
+                        const float* d_y, int32_t n_rows, const int32_t* d_idx, int32_t n,
+                        float* d_grad, float* d_loss, int32_t flags, void* d_workspace,
+                        size_t bytes, void* hip_stream);
+
+/* One Adam update (Kingma and Ba, 2015, with bias correction) of the
+ * parameters with moment buffers d_m, d_v (LBM_MLP_NPARAMS floats each,
+ * zero before step t = 1). */
+lbm_status lbm_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t t,
+                        float lr, float beta1, float beta2, float eps, void* hip_stream);
+
+/* lbm_mlp_grad followed by lbm_mlp_adam with beta1 = 0.9, beta2 = 0.999,
+ * eps = 1e-8. */
+lbm_status lbm_mlp_train_step(float* d_params, float* d_m, float* d_v, int64_t t, float lr,
+                              const lbm_mlp_norm* norm, const float* d_x, const float* d_y,
+                              int32_t n_rows, const int32_t* d_idx, int32_t n, float* d_grad,
+                              float* d_loss, int32_t flags, void* d_workspace, size_t bytes,
+                              void* hip_stream);
 
 #ifdef __cplusplus
 }

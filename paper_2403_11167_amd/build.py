@@ -16,6 +16,7 @@ import sys
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 SOURCES = [os.path.join(_HERE, "csrc", "lbm_kernels.hip"),
+           os.path.join(_HERE, "csrc", "mlp_kernels.hip"),
            os.path.join(_HERE, "csrc", "thermo.cpp")]
 OUT = os.path.join(_HERE, "liblbm.so")
 

@@ -1,0 +1,314 @@
+"""Calibration runs: equilibrium properties of the two models as functions of
+(model, Tr, width parameter w, kappa), computed by batches of lattices.
+
+The paper sets the pseudopotential parameters by theory (Sec. 3, App. B:
+sigma^Li from the mechanical-stability condition; Sec. 4 / App. C: kappa^P
+for the interface width, kappa^Li for the surface tension) and notes that
+at low Tr they must instead be found by preliminary simulations (Sec. 5.1,
+5.2).  A calibration unit here is one flat-interface and one droplet
+lattice per tuple, run to equilibrium in a batch; the labels are
+
+  rho_l, rho_v  bulk densities of the flat interface (Sec. 5.1),
+  W             its max-slope width (rho_l - rho_v) / max |d_x rho|,
+  sigma         surface tension from Laplace's law, dp * R (Sec. 5.2).
+
+Tuple meaning (both models share the EOS: Carnahan-Starling, a = 0.25,
+b = 4, R = 1, the EOS of the paper's Sec. 5.1 runs):
+  kappa is the reduced gradient coefficient kappa_FE / a.  At fixed Tr the
+      pressure scales with a, so the planar free-energy profile (Eq. 26)
+      depends on kappa_FE / a only; kappa = 2 is the paper's a = 0.25,
+      kappa_FE = 0.5 pair.  (Taking kappa_FE = kappa directly puts most of
+      the range beyond the free-energy model's short-wave stability limit,
+      which a uniform liquid at rest already shows near kappa_FE rho_l = 1/3.)
+  P   sigma^Li from App. B at Tr; kappa^P so that the Eq. 44 max-slope width
+      equals w; kappa^Li so that the Eq. 46 surface tension equals the FE
+      one (Eq. 26) at kappa_FE.  tau = 1 except tau_q = 1/1.99 (Sec. 5.2).
+  FE  kappa_FE = a kappa; tau = 1 except tau_e = 0.75 (Sec. 5.1).
+Plain initial profiles are tanh profiles between the Maxwell densities with
+width w (FE: width w as well; its equilibrium width is set by kappa).
+Seeded initial profiles use predicted (rho_l, rho_v, W) instead.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import inputs, lbm
+
+EOS = lbm.EOS_CS
+A, B, RGAS = 0.25, 4.0, 1.0
+TR_RANGE = (0.5, 0.95)
+W_RANGE = (2.0, 8.0)
+KAPPA_RANGE = (0.5, 2.0)
+SIZES = (64, 128, 256, 512)
+
+
+@dataclass
+class Tuple4:
+    model: int
+    Tr: float
+    w: float
+    kappa: float
+
+
+def sample_tuples(n: int, seed: int):
+    """n tuples with model uniform in {P, FE}, Tr ~ U[0.5, 0.95],
+    w ~ U[2, 8], kappa ~ U[0.5, 2] (numpy default_rng(seed))."""
+    rng = np.random.default_rng(seed)
+    return [Tuple4(int(rng.integers(0, 2)), float(rng.uniform(*TR_RANGE)),
+                   float(rng.uniform(*W_RANGE)), float(rng.uniform(*KAPPA_RANGE)))
+            for _ in range(n)]
+
+
+def sample_sizes(n: int, seed: int):
+    rng = np.random.default_rng(seed + 1000)
+    return [int(SIZES[rng.integers(0, len(SIZES))]) for _ in range(n)]
+
+
+_TC = None
+
+
+def critical_T():
+    global _TC
+    if _TC is None:
+        _TC = lbm.eos_critical(EOS, A, B, RGAS)[0]
+    return _TC
+
+
+def kappa_fe(t: Tuple4) -> float:
+    return A * t.kappa
+
+
+def model_config(t: Tuple4, nx: int, ny: int, precision: int) -> lbm.Config:
+    T = t.Tr * critical_T()
+    tau = [1.0] * 9
+    if t.model == lbm.MODEL_P:
+        sig, kp, kli = lbm.match_p_to_fe(EOS, A, B, RGAS, T, kappa_fe(t), t.w)
+        tau[4] = tau[6] = 1.0 / 1.99
+        return lbm.Config(nx, ny, lbm.MODEL_P, EOS, A, B, RGAS, T, tau=tau, sigma_li=sig,
+                          kappa_p=kp, kappa_li=kli, precision=precision)
+    tau[1] = 0.75
+    return lbm.Config(nx, ny, lbm.MODEL_FE, EOS, A, B, RGAS, T, tau=tau, kappa=kappa_fe(t),
+                      precision=precision)
+
+
+def initial_guess(t: Tuple4):
+    """Plain initial profile parameters: Maxwell densities and width w."""
+    T = t.Tr * critical_T()
+    rl, rv, _ = lbm.maxwell(EOS, A, B, RGAS, T)
+    return rl, rv, t.w
+
+
+def flat_rho0(L: int, ny: int, rl: float, rv: float, W: float):
+    return inputs.planar_slab(L, ny, rl, rv, width=max(W, 1.0))
+
+
+def droplet_rho0(L: int, rl: float, rv: float, W: float):
+    return inputs.droplet(L, L, rl, rv, radius=L / 5.0, width=max(W, 1.0))
+
+
+def flat_labels(rho: np.ndarray):
+    """(rho_l, rho_v, W) of a flat-interface equilibrium (rows identical)."""
+    prof = rho.mean(axis=0)
+    rl, rv = float(prof.max()), float(prof.min())
+    slope = np.abs(np.roll(prof, -1) - np.roll(prof, 1)).max() / 2
+    return rl, rv, (rl - rv) / slope if slope > 0 else float("nan")
+
+
+def droplet_sigma(obs: dict) -> float:
+    """Laplace's law in 2-D: sigma = dp R with the equimolar radius."""
+    return float(obs["dp"] * obs["r_equimolar"])
+
+
+def _shape(size):
+    """(flat nx, flat ny, droplet L) from an int L (both L x L) or a triple."""
+    if isinstance(size, (tuple, list)):
+        return tuple(int(v) for v in size)
+    return int(size), int(size), int(size)
+
+
+def build_problems(tuples, sizes, precision, guesses=None):
+    """Configs and initial fields for one flat and one droplet lattice per
+    tuple.  sizes: per tuple an int L (flat and droplet L x L) or a triple
+    (flat nx, flat ny, droplet L).  guesses: per-tuple (rho_l, rho_v, W)
+    (None: plain guesses)."""
+    cfgs, rho0s, meta = [], [], []
+    for k, (t, size) in enumerate(zip(tuples, sizes)):
+        rl, rv, W = guesses[k] if guesses is not None else initial_guess(t)
+        fx, fy, L = _shape(size)
+        cfgs.append(model_config(t, fx, fy, precision))
+        rho0s.append(flat_rho0(fx, fy, rl, rv, W))
+        meta.append((k, "flat"))
+        cfgs.append(model_config(t, L, L, precision))
+        rho0s.append(droplet_rho0(L, rl, rv, W))
+        meta.append((k, "droplet"))
+    return cfgs, rho0s, meta
+
+
+def run_calibration(tuples, sizes, precision=lbm.FP32_SHIFTED, guesses=None,
+                    check_every=200, du_tol=1e-9, max_steps=200000):
+    """Run the flat + droplet pair of every tuple to equilibrium in one batch.
+    Returns (labels, info): labels[k] = dict(rho_l, rho_v, W, sigma, ok) and
+    info = dict(seconds, steps, states, steps_per_problem, ...).  The timed
+    region covers building the batch (initial populations on the device)
+    and running it to retirement."""
+    import time
+
+    import torch
+    dev = torch.device("cuda:0")
+    cfgs, rho0s, meta = build_problems(tuples, sizes, precision, guesses)
+    t0 = time.perf_counter()
+    batch = lbm.Batch(cfgs, [torch.from_numpy(r).to(dev) for r in rho0s])
+    steps = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps)
+    labels = measure(batch, cfgs, meta, len(tuples))
+    seconds = time.perf_counter() - t0
+    states, nsteps, du, flags = batch.state()
+    batch.close()
+    units = sum(1 for lab in labels if lab["ok"])
+    info = dict(seconds=seconds, steps=steps, states=states, steps_per_problem=nsteps,
+                problems=len(cfgs), converged_units=units,
+                units_per_second=units / seconds if seconds > 0 else math.nan)
+    return labels, info
+
+
+def measure(batch, cfgs, meta, ntuples, which=None, labels=None,
+            accept=(lbm.BATCH_CONVERGED,)):
+    """Labels of every tuple (or of the tuple indices in `which`, updating
+    `labels`) from the batch's current state.  A tuple is ok when both of its
+    lattices are in an accepted state, finite, and its droplet is still a
+    droplet."""
+    states = batch.state()[0]
+    if labels is None:
+        labels = [dict(rho_l=math.nan, rho_v=math.nan, W=math.nan, sigma=math.nan, ok=True)
+                  for _ in range(ntuples)]
+    sel = set(range(ntuples)) if which is None else set(which)
+    for k in sel:
+        labels[k]["ok"] = True
+    for i, (k, kind) in enumerate(meta):
+        if k not in sel:
+            continue
+        labels[k]["ok"] = labels[k]["ok"] and states[i] in accept
+        if kind == "flat":
+            _, (rho, _, _) = batch.observe(i, fields=True)
+            rl, rv, W = flat_labels(rho.cpu().numpy())
+            labels[k].update(rho_l=rl, rho_v=rv, W=W)
+        else:
+            L = cfgs[i].nx
+            obs = batch.observe(i, L // 2, L // 2)
+            labels[k]["sigma"] = droplet_sigma(obs)
+            labels[k]["drop_contrast"] = float(obs["rho_in"] - obs["rho_out"])
+    for k in sel:
+        lab = labels[k]
+        # a droplet that dissolved (or a vapour bubble) measures no surface tension
+        if not (lab.get("drop_contrast", 0.0) > 0.5 * (lab["rho_l"] - lab["rho_v"])):
+            lab["ok"] = False
+    return labels
+
+
+CS_LATTICE = 1.0 / math.sqrt(3.0)
+
+
+def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
+                           check_every=200, du_tol=1e-9, max_steps=200000,
+                           crossings=8.0, rtol_rho=0.01, rtol_sigma=0.03, rtol_w=0.05):
+    """Calibration with the surrogate in front of the method.
+
+    1. The surrogate predicts (rho_l, rho_v, sigma, W) for every tuple and
+       seeds both lattices with tanh profiles of the predicted densities and
+       width.
+    2. Verification: each lattice runs at most `crossings` sound crossings
+       of its box (max(nx, ny) / c_s steps each), retiring earlier if it
+       converges.
+    3. A tuple whose measured labels agree with the prediction (densities
+       within rtol_rho, sigma within rtol_sigma, W within rtol_w) is done
+       with the measured labels; every other tuple keeps running from its
+       current state to the plain method's convergence criterion (the
+       fallback).
+    Returns (labels, info) like run_calibration, info with the number of
+    tuples accepted after verification and the prediction array."""
+    import time
+
+    import torch
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    pred = surrogate.predict(features(tuples))
+    cfgs, rho0s, meta = build_problems(tuples, sizes, precision, seeded_guesses(pred))
+    batch = lbm.Batch(cfgs, [torch.from_numpy(r).to(dev) for r in rho0s])
+    for i, c in enumerate(cfgs):
+        v = crossings * max(c.nx, c.ny) / CS_LATTICE
+        batch.set_limit(i, int(math.ceil(v / check_every)) * check_every)
+    steps = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps)
+    labels = measure(batch, cfgs, meta, len(tuples),
+                     accept=(lbm.BATCH_CONVERGED, lbm.BATCH_MAXSTEPS))
+    accepted, fallback = [], []
+    for k, lab in enumerate(labels):
+        p = pred[k]
+        agree = (lab["ok"] and abs(lab["rho_l"] / p[0] - 1) <= rtol_rho
+                 and abs(lab["rho_v"] / p[1] - 1) <= rtol_rho
+                 and abs(lab["sigma"] / p[2] - 1) <= rtol_sigma
+                 and abs(lab["W"] / p[3] - 1) <= rtol_w)
+        (accepted if agree else fallback).append(k)
+    states = batch.state()[0]
+    fb = set(fallback)
+    resume = [i for i, (k, _) in enumerate(meta) if k in fb and states[i] == lbm.BATCH_MAXSTEPS]
+    for i in resume:
+        batch.set_limit(i, 2 ** 62)
+    steps2 = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps) if resume else 0
+    if fallback:
+        measure(batch, cfgs, meta, len(tuples), which=fallback, labels=labels)
+    seconds = time.perf_counter() - t0
+    states, nsteps, du, flags = batch.state()
+    batch.close()
+    units = sum(1 for lab in labels if lab["ok"])
+    info = dict(seconds=seconds, steps=steps + steps2, states=states, steps_per_problem=nsteps,
+                problems=len(cfgs), converged_units=units,
+                units_per_second=units / seconds if seconds > 0 else math.nan,
+                accepted=len(accepted), fallback=len(fallback), prediction=pred)
+    return labels, info
+
+
+def features(tuples) -> np.ndarray:
+    """Surrogate inputs (model, Tr, w, kappa)."""
+    return np.array([[t.model, t.Tr, t.w, t.kappa] for t in tuples], dtype=np.float64)
+
+
+def targets(labels) -> np.ndarray:
+    """Surrogate outputs (rho_l, rho_v, sigma, W)."""
+    return np.array([[l["rho_l"], l["rho_v"], l["sigma"], l["W"]] for l in labels],
+                    dtype=np.float64)
+
+
+def valid(labels):
+    """Mask of tuples whose flat and droplet lattices both converged to a
+    two-phase state with finite labels."""
+    y = targets(labels)
+    return np.array([lab["ok"] for lab in labels]) & np.all(np.isfinite(y), axis=1) & \
+        np.all(y > 0, axis=1)
+
+
+def training_set(n_tuples: int, seed: int, size=(64, 8, 128), **kw):
+    """Calibration labels for n_tuples sampled tuples on small lattices
+    (flat 64 x 8, droplet 128 x 128 by default): (features, targets, info)
+    with only valid tuples kept."""
+    tuples = sample_tuples(n_tuples, seed)
+    labels, info = run_calibration(tuples, [size] * n_tuples, **kw)
+    m = valid(labels)
+    return features(tuples)[m], targets(labels)[m], info
+
+
+def seeded_guesses(pred):
+    """Initial-profile parameters (rho_l, rho_v, W) from surrogate
+    predictions (n x 4: rho_l, rho_v, sigma, W)."""
+    return [(float(p[0]), float(p[1]), float(p[3])) for p in pred]
+
+
+def compare(labels_a, labels_b):
+    """Relative differences of b against a on tuples valid in both:
+    dict(rho_l, rho_v, sigma, W) of arrays, plus the mask."""
+    m = valid(labels_a) & valid(labels_b)
+    ya, yb = targets(labels_a)[m], targets(labels_b)[m]
+    rel = np.abs(yb / ya - 1)
+    return {k: rel[:, i] for i, k in enumerate(("rho_l", "rho_v", "sigma", "W"))}, m
+

@@ -1687,6 +1687,7 @@ struct BatchInst {
   int stall;        // checks without a new best du
   int checks;
   uint32_t flags;
+  int64_t limit;    // retire with LBM_BATCH_MAXSTEPS once steps >= limit
 };
 
 struct GroupKey {
@@ -1707,6 +1708,7 @@ struct lbm_batch {
   char* ws;
   std::vector<BatchInst> inst;
   size_t desc_off, tiles_off, du_off, tiles_cap;
+  size_t flagptr_off, flagout_off;  // per-instance flag pointers, gathered flags
   int parity;  // common population parity of all instances
   // one tile table per (model, EOS, strip width) group, all in one buffer
   std::vector<std::pair<GroupKey, std::pair<int, int>>> groups;  // key -> (offset, count)
@@ -1720,7 +1722,7 @@ namespace {
 
 struct BatchLayout {
   std::vector<size_t> inst_off, chk_off;
-  size_t desc_off, tiles_off, du_off, total, tiles_cap;
+  size_t desc_off, tiles_off, du_off, flagptr_off, flagout_off, total, tiles_cap;
 };
 
 BatchLayout make_batch_layout(int n, const lbm_params* p) {
@@ -1745,6 +1747,10 @@ BatchLayout make_batch_layout(int n, const lbm_params* p) {
   off += align_up(tiles * sizeof(BatchTile));
   B.du_off = off;
   off += align_up(n * sizeof(unsigned long long));
+  B.flagptr_off = off;
+  off += align_up(n * sizeof(unsigned*));
+  B.flagout_off = off;
+  off += align_up(n * sizeof(unsigned));
   B.total = off;
   return B;
 }
@@ -1829,6 +1835,13 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
+// Copies every lattice's sticky flags into one array, so that a check reads
+// them with a single transfer.
+__global__ void k_gather_flags(const unsigned* const* __restrict__ ptrs, unsigned* out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = *ptrs[i];
+}
+
 void drop_graph(lbm_batch* b) {
   if (b->graph) hipGraphExecDestroy(b->graph);
   b->graph = nullptr;
@@ -1850,6 +1863,9 @@ lbm_status capture_chunk(lbm_batch* b, int steps) {
   hipLaunchKernelGGL(k_zero_u64, dim3((b->n + 255) / 256), dim3(256), 0, b->cap_stream,
                      (unsigned long long*)(b->ws + b->du_off), b->n);
   batch_step(b, 1);
+  hipLaunchKernelGGL(k_gather_flags, dim3((b->n + 255) / 256), dim3(256), 0, b->cap_stream,
+                     (const unsigned* const*)(b->ws + b->flagptr_off),
+                     (unsigned*)(b->ws + b->flagout_off), b->n);
   hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
   b->launch = b->stream;
   b->parity = parity0;  // capture only recorded the launches
@@ -1922,6 +1938,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
   b->desc_off = B.desc_off;
   b->tiles_off = B.tiles_off;
   b->du_off = B.du_off;
+  b->flagptr_off = B.flagptr_off;
+  b->flagout_off = B.flagout_off;
   b->tiles_cap = B.tiles_cap;
   b->parity = 0;
   b->tables_valid = false;
@@ -1931,7 +1949,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
   std::vector<double> h;
   for (int i = 0; i < n && st == LBM_OK; ++i) {
     BatchInst& I = b->inst[i];
-    I = BatchInst{nullptr, B.chk_off[i], LBM_BATCH_ACTIVE, 0, INFINITY, INFINITY, 0, 0, 0u};
+    I = BatchInst{nullptr, B.chk_off[i], LBM_BATCH_ACTIVE, 0, INFINITY, INFINITY, 0, 0, 0u,
+                  INT64_MAX};
     st = read_host(d_rho0[i], (size_t)p[i].nx * p[i].ny, stream, h);
     if (st == LBM_OK) st = ctx_setup(&p[i], b->ws + B.inst_off[i], d_rho0[i], h, stream, &I.ctx);
   }
@@ -1944,7 +1963,10 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
   // instance descriptors
   size_t dsz = b->fp64 ? sizeof(InstDesc<double>) : sizeof(InstDesc<float>);
   std::vector<char> descs(n * dsz);
+  std::vector<unsigned*> flagptrs(n);
   for (int i = 0; i < n; ++i) {
+    lbm_ctx* c = b->inst[i].ctx;
+    flagptrs[i] = (unsigned*)(c->ws + c->L.flags);
     if (b->fp64) {
       InstDesc<double> d = make_desc<double>(b, b->inst[i]);
       d.du = (unsigned long long*)(b->ws + b->du_off) + i;
@@ -1957,6 +1979,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
   }
   if (hipMemcpyAsync(b->ws + b->desc_off, descs.data(), descs.size(), hipMemcpyHostToDevice,
                      stream) != hipSuccess ||
+      hipMemcpyAsync(b->ws + b->flagptr_off, flagptrs.data(), n * sizeof(unsigned*),
+                     hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
     for (auto& I : b->inst) delete I.ctx;
     hipStreamDestroy(b->cap_stream);
@@ -1978,7 +2002,13 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
   lbm_status st = LBM_OK;
   while (done < max_steps) {
     bool any = false;
-    for (auto& I : b->inst) any |= (I.state == LBM_BATCH_ACTIVE);
+    for (auto& I : b->inst) {
+      if (I.state == LBM_BATCH_ACTIVE && I.steps >= I.limit) {
+        I.state = LBM_BATCH_MAXSTEPS;
+        b->tables_valid = false;
+      }
+      any |= (I.state == LBM_BATCH_ACTIVE);
+    }
     if (!any) break;
     if (!b->tables_valid) {
       if ((st = rebuild_tables(b)) != LBM_OK) break;
@@ -1993,13 +2023,8 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
     done += chunk;
     if (hipMemcpyAsync(du_bits.data(), b->ws + b->du_off, b->n * sizeof(unsigned long long),
                        hipMemcpyDeviceToHost, b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
-    for (int i = 0; i < b->n; ++i) {
-      lbm_ctx* c = b->inst[i].ctx;
-      if (b->inst[i].state != LBM_BATCH_ACTIVE) continue;
-      if (hipMemcpyAsync(&fl[i], c->ws + c->L.flags, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                         b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
-    }
-    if (st != LBM_OK) break;
+    if (hipMemcpyAsync(fl.data(), b->ws + b->flagout_off, b->n * sizeof(uint32_t),
+                       hipMemcpyDeviceToHost, b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
     if (hipStreamSynchronize(b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
     for (int i = 0; i < b->n; ++i) {
       BatchInst& I = b->inst[i];
@@ -2046,6 +2071,25 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
   }
   if (steps_run) *steps_run = done;
   return st;
+}
+
+lbm_status lbm_batch_set_limit(lbm_batch* b, int32_t i, int64_t max_steps) {
+  if (!b || i < 0 || i >= b->n || max_steps < 0) return LBM_ERR_INVALID_ARG;
+  BatchInst& I = b->inst[i];
+  I.limit = max_steps;
+  if (I.state == LBM_BATCH_ACTIVE && I.steps >= max_steps) {
+    I.state = LBM_BATCH_MAXSTEPS;
+    b->tables_valid = false;
+  } else if (I.state == LBM_BATCH_MAXSTEPS && I.steps < max_steps) {
+    // resume from the current state; the next check measures du against
+    // velocities stored by this one, so it only stores them again
+    I.state = LBM_BATCH_ACTIVE;
+    I.checks = 0;
+    I.stall = 0;
+    I.best_du = INFINITY;
+    b->tables_valid = false;
+  }
+  return LBM_OK;
 }
 
 lbm_status lbm_batch_state(lbm_batch* b, int32_t* state, int64_t* steps, double* du,

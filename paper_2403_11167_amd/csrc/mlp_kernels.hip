@@ -1,0 +1,474 @@
+// Calibration surrogate: a 4 -> 128 -> 128 -> 128 -> 4 multilayer perceptron
+// with GELU hidden activations (Hendrycks and Gimpel, 2016), mapping a
+// calibration tuple (model, Tr, width parameter, kappa) to the equilibrium
+// properties (rho_l, rho_v, surface tension, interface width), trained with
+// Adam (Kingma and Ba, 2015) on equilibria computed by the batched lattices.
+//
+// Kernels (gfx950):
+//   k_mlp_forward  tile of 16 samples per 256-thread workgroup; layer inputs
+//                  kept in LDS, weights streamed from L2 with reads that are
+//                  contiguous across the output index;
+//   k_mlp_grad     forward, loss and back-propagation of a tile in one
+//                  workgroup; a workgroup walks several tiles and accumulates
+//                  its weight gradient in its own slice of the workspace; for
+//                  the transposed products the 128 x 128 weight matrix is
+//                  staged in LDS with rows padded to 129 words (no bank
+//                  conflicts); ~130 KB LDS per workgroup;
+//   k_mlp_reduce   sums the per-workgroup slices in a fixed order, so the
+//                  gradient is deterministic;
+//   k_mlp_adam     one elementwise Adam update.
+// The network is ~34k parameters: every launch is latency-bound, not bound
+// by HBM or the matrix units, so the products run on the vector ALUs.
+//
+// BF16 mode rounds every product operand (layer inputs and weights) to
+// bfloat16, round to nearest even; products of two bfloat16 values are exact
+// in FP32 and all sums accumulate in FP32.  Biases and back-propagated
+// errors are not rounded; the weight rounding is treated as the identity in
+// the gradient.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace mlpk {
+
+constexpr int H = 128, NI = 4, NO = 4;
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + NI * H;
+constexpr int OFF_W2 = OFF_B1 + H;
+constexpr int OFF_B2 = OFF_W2 + H * H;
+constexpr int OFF_W3 = OFF_B2 + H;
+constexpr int OFF_B3 = OFF_W3 + H * H;
+constexpr int OFF_W4 = OFF_B3 + H;
+constexpr int OFF_B4 = OFF_W4 + H * NO;
+constexpr int NPARAM = OFF_B4 + NO;
+static_assert(NPARAM == LBM_MLP_NPARAMS, "parameter count");
+constexpr int TS = 16;         // samples per tile
+constexpr int NT = 256;        // threads per workgroup
+constexpr int HALF = TS / 2;   // samples per thread in the 128-wide phases
+constexpr int WPAD = H + 1;    // padded LDS row
+constexpr int MAX_GRAD_BLOCKS = 128;
+
+struct Norm {
+  float xs[NI], xk[NI], ys[NO], yk[NO];
+};
+
+__device__ __forceinline__ float bf16r(float v) {
+  unsigned u = __float_as_uint(v);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(u);
+}
+
+template <int BF>
+__device__ __forceinline__ float rnd(float v) {
+  if constexpr (BF) return bf16r(v);
+  else return v;
+}
+
+__device__ __forceinline__ float gelu(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+
+__device__ __forceinline__ float gelu_d(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Forward pass of one tile.  s_a0: [TS][NI] rounded inputs (already set);
+// s_z: [3][TS][H] pre-activations; s_a: [3][TS][H] rounded activations;
+// s_o: [TS][NO] outputs in normalised log space.  Sample rows >= nv hold
+// zero inputs and finite values that the callers ignore.
+template <int BF>
+__device__ void forward_tile(const float* __restrict__ P, const float (*s_a0)[NI],
+                             float (*s_z)[TS][H], float (*s_a)[TS][H], float (*s_o)[NO]) {
+  const int t = threadIdx.x;
+  const int j = t & (H - 1), sh = (t >> 7) * HALF;
+  {
+    float acc[HALF];
+    const float b = P[OFF_B1 + j];
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) acc[q] = b;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const float w = rnd<BF>(P[OFF_W1 + k * H + j]);
+#pragma unroll
+      for (int q = 0; q < HALF; ++q) acc[q] = fmaf(w, s_a0[sh + q][k], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) {
+      s_z[0][sh + q][j] = acc[q];
+      s_a[0][sh + q][j] = rnd<BF>(gelu(acc[q]));
+    }
+  }
+  __syncthreads();
+  for (int l = 1; l < 3; ++l) {
+    const float* W = P + (l == 1 ? OFF_W2 : OFF_W3);
+    float acc[HALF];
+    const float b = P[(l == 1 ? OFF_B2 : OFF_B3) + j];
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) acc[q] = b;
+    for (int k = 0; k < H; ++k) {
+      const float w = rnd<BF>(W[k * H + j]);
+#pragma unroll
+      for (int q = 0; q < HALF; ++q) acc[q] = fmaf(w, s_a[l - 1][sh + q][k], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) {
+      s_z[l][sh + q][j] = acc[q];
+      s_a[l][sh + q][j] = rnd<BF>(gelu(acc[q]));
+    }
+    __syncthreads();
+  }
+  if (t < TS * NO) {
+    const int s = t / NO, o = t % NO;
+    float acc = P[OFF_B4 + o];
+    for (int k = 0; k < H; ++k) acc = fmaf(rnd<BF>(P[OFF_W4 + k * NO + o]), s_a[2][s][k], acc);
+    s_o[s][o] = acc;
+  }
+  __syncthreads();
+}
+
+template <int BF>
+__device__ __forceinline__ void load_inputs(const float* __restrict__ X, const Norm& nm, int s0,
+                                            int nv, float (*s_a0)[NI], const int* __restrict__ idx,
+                                            int nrows, bool* bad) {
+  const int t = threadIdx.x;
+  if (t < TS * NI) {
+    const int s = t / NI, k = t % NI;
+    float v = 0.0f;
+    if (s < nv) {
+      const int r = idx ? idx[s0 + s] : s0 + s;
+      if (r >= 0 && r < nrows) v = rnd<BF>((X[(size_t)r * NI + k] - nm.xs[k]) * nm.xk[k]);
+      else *bad = true;
+    }
+    s_a0[s][k] = v;
+  }
+}
+
+template <int BF>
+__global__ __launch_bounds__(NT) void k_mlp_forward(const float* __restrict__ P, Norm nm,
+                                                    const float* __restrict__ X, int n,
+                                                    float* __restrict__ Y) {
+  __shared__ float s_a0[TS][NI];
+  __shared__ float s_z[3][TS][H];
+  __shared__ float s_a[3][TS][H];
+  __shared__ float s_o[TS][NO];
+  const int s0 = blockIdx.x * TS;
+  const int nv = min(TS, n - s0);
+  bool bad = false;
+  load_inputs<BF>(X, nm, s0, nv, s_a0, nullptr, n, &bad);
+  __syncthreads();
+  forward_tile<BF>(P, s_a0, s_z, s_a, s_o);
+  const int t = threadIdx.x;
+  if (t < TS * NO) {
+    const int s = t / NO, o = t % NO;
+    if (s < nv) Y[(size_t)(s0 + s) * NO + o] = expf(s_o[s][o] * nm.yk[o] + nm.ys[o]);
+  }
+}
+
+// Gradient slice update: the first tile of a workgroup stores, later tiles
+// add.  Each slice element is owned by one thread in every phase, the same
+// thread for every tile.
+__device__ __forceinline__ void gput(float* p, float g, bool first) {
+  if (first) *p = g;
+  else *p += g;
+}
+
+// Loss and gradient partials.  Workgroup g handles tiles g, g + G, ...
+// (G <= number of tiles, so every workgroup has at least one); its gradient
+// slice part[g * NPARAM ...] and loss partial lpart[g] are fully written by
+// this kernel (no prior clearing needed).
+template <int BF>
+__global__ __launch_bounds__(NT) void k_mlp_grad(const float* __restrict__ P, Norm nm,
+                                                 const float* __restrict__ X,
+                                                 const float* __restrict__ Y,
+                                                 const int* __restrict__ idx, int n, int nrows,
+                                                 float scale, float* __restrict__ part,
+                                                 float* __restrict__ lpart) {
+  __shared__ float s_a0[TS][NI];
+  __shared__ float s_z[3][TS][H];
+  __shared__ float s_a[3][TS][H];
+  __shared__ float s_d[TS][H];   // dL/dz of the current layer
+  __shared__ float s_e[TS][H];   // dL/dz of the layer below
+  __shared__ float s_w[H][WPAD];
+  __shared__ float s_o[TS][NO];  // outputs, then dL/dout
+  __shared__ float s_l[NT / 64];
+  __shared__ int s_bad;
+  const int t = threadIdx.x;
+  const int j = t & (H - 1), hsel = t >> 7, sh = hsel * HALF;
+  float* G = part + (size_t)blockIdx.x * NPARAM;
+  if (t == 0) s_bad = 0;
+  __syncthreads();
+  float lacc = 0.0f;
+  const int ntiles = (n + TS - 1) / TS;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int s0 = tile * TS;
+    const int nv = min(TS, n - s0);
+    const bool first = tile == (int)blockIdx.x;
+    bool bad = false;
+    load_inputs<BF>(X, nm, s0, nv, s_a0, idx, nrows, &bad);
+    if (bad) s_bad = 1;
+    __syncthreads();
+    forward_tile<BF>(P, s_a0, s_z, s_a, s_o);
+    // loss and dL/dout (zero for padding rows and rejected indices)
+    float dv = 0.0f;
+    if (t < TS * NO) {
+      const int s = t / NO, o = t % NO;
+      if (s < nv) {
+        const int r = idx ? idx[s0 + s] : s0 + s;
+        if (r >= 0 && r < nrows) {
+          const float tgt = (logf(Y[(size_t)r * NO + o]) - nm.ys[o]) / nm.yk[o];
+          const float res = s_o[s][o] - tgt;
+          lacc = fmaf(res, res, lacc);
+          dv = 2.0f * res * scale;
+        }
+      }
+    }
+    __syncthreads();  // every output read before it is overwritten
+    if (t < TS * NO) s_o[t / NO][t % NO] = dv;
+    __syncthreads();
+    // output layer: dW4[k][o] = sum_s a3[s][k] dout[s][o]
+    for (int e = t; e < H * NO; e += NT) {
+      const int k = e / NO, o = e % NO;
+      float g = 0.0f;
+#pragma unroll
+      for (int s = 0; s < TS; ++s) g = fmaf(s_a[2][s][k], s_o[s][o], g);
+      gput(&G[OFF_W4 + e], g, first);
+    }
+    if (t < NO) {
+      float g = 0.0f;
+#pragma unroll
+      for (int s = 0; s < TS; ++s) g += s_o[s][t];
+      gput(&G[OFF_B4 + t], g, first);
+    }
+    {
+      float w[NO];
+#pragma unroll
+      for (int o = 0; o < NO; ++o) w[o] = rnd<BF>(P[OFF_W4 + j * NO + o]);
+#pragma unroll
+      for (int q = 0; q < HALF; ++q) {
+        const int s = sh + q;
+        float da = 0.0f;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) da = fmaf(s_o[s][o], w[o], da);
+        s_d[s][j] = da * gelu_d(s_z[2][s][j]);
+      }
+    }
+    __syncthreads();
+    // hidden layers 3 and 2: input activations s_a[l - 1], weights W_{l+1}
+    for (int l = 2; l >= 1; --l) {
+      const int offw = (l == 2) ? OFF_W3 : OFF_W2;
+      const int offb = (l == 2) ? OFF_B3 : OFF_B2;
+      const float* W = P + offw;
+      for (int e = t; e < H * H; e += NT) s_w[e >> 7][e & (H - 1)] = rnd<BF>(W[e]);
+      {
+        float dz[TS];
+#pragma unroll
+        for (int s = 0; s < TS; ++s) dz[s] = s_d[s][j];
+        for (int m = 0; m < H / 2; ++m) {
+          const int k = hsel + 2 * m;
+          float g = 0.0f;
+#pragma unroll
+          for (int s = 0; s < TS; ++s) g = fmaf(s_a[l - 1][s][k], dz[s], g);
+          gput(&G[offw + k * H + j], g, first);
+        }
+        if (hsel == 0) {
+          float g = 0.0f;
+#pragma unroll
+          for (int s = 0; s < TS; ++s) g += dz[s];
+          gput(&G[offb + j], g, first);
+        }
+      }
+      __syncthreads();  // weights staged
+      {
+        float acc[HALF];
+#pragma unroll
+        for (int q = 0; q < HALF; ++q) acc[q] = 0.0f;
+        for (int jj = 0; jj < H; ++jj) {
+          const float w = s_w[j][jj];
+#pragma unroll
+          for (int q = 0; q < HALF; ++q) acc[q] = fmaf(s_d[sh + q][jj], w, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < HALF; ++q) s_e[sh + q][j] = acc[q] * gelu_d(s_z[l - 1][sh + q][j]);
+      }
+      __syncthreads();
+      for (int e = t; e < TS * H; e += NT) s_d[e >> 7][e & (H - 1)] = s_e[e >> 7][e & (H - 1)];
+      __syncthreads();
+    }
+    // first layer: dW1[k][j] = sum_s a0[s][k] dz1[s][j]
+    {
+      float dz[TS];
+#pragma unroll
+      for (int s = 0; s < TS; ++s) dz[s] = s_d[s][j];
+#pragma unroll
+      for (int m = 0; m < NI / 2; ++m) {
+        const int k = hsel + 2 * m;
+        float g = 0.0f;
+#pragma unroll
+        for (int s = 0; s < TS; ++s) g = fmaf(s_a0[s][k], dz[s], g);
+        gput(&G[OFF_W1 + k * H + j], g, first);
+      }
+      if (hsel == 0) {
+        float g = 0.0f;
+#pragma unroll
+        for (int s = 0; s < TS; ++s) g += dz[s];
+        gput(&G[OFF_B1 + j], g, first);
+      }
+    }
+    __syncthreads();  // LDS reused by the next tile
+  }
+  // loss partial of this workgroup
+  for (int off = 32; off > 0; off >>= 1) lacc += __shfl_down(lacc, off, 64);
+  if ((t & 63) == 0) s_l[t >> 6] = lacc;
+  __syncthreads();
+  if (t == 0) {
+    float s = 0.0f;
+    for (int w = 0; w < NT / 64; ++w) s += s_l[w];
+    lpart[blockIdx.x] = s_bad ? NAN : s;
+  }
+}
+
+__global__ void k_mlp_reduce(const float* __restrict__ part, const float* __restrict__ lpart,
+                             int nblk, float scale, float* __restrict__ grad,
+                             float* __restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < NPARAM) {
+    float g = 0.0f;
+    for (int b = 0; b < nblk; ++b) g += part[(size_t)b * NPARAM + p];
+    grad[p] = g;
+  }
+  if (p == 0 && loss) {
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += lpart[b];
+    *loss = s * scale;
+  }
+}
+
+__global__ void k_mlp_adam(float* __restrict__ P, float* __restrict__ M, float* __restrict__ V,
+                           const float* __restrict__ G, float lr, float b1, float b2, float eps,
+                           float bc1, float bc2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  const float g = G[p];
+  const float m = b1 * M[p] + (1.0f - b1) * g;
+  const float v = b2 * V[p] + (1.0f - b2) * g * g;
+  M[p] = m;
+  V[p] = v;
+  P[p] -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+}
+
+Norm to_norm(const lbm_mlp_norm* n) {
+  Norm r;
+  for (int i = 0; i < NI; ++i) {
+    r.xs[i] = n->x_shift[i];
+    r.xk[i] = n->x_scale[i];
+  }
+  for (int i = 0; i < NO; ++i) {
+    r.ys[i] = n->y_shift[i];
+    r.yk[i] = n->y_scale[i];
+  }
+  return r;
+}
+
+bool norm_ok(const lbm_mlp_norm* n) {
+  for (int i = 0; i < NO; ++i)
+    if (!(n->y_scale[i] != 0.0f) || !isfinite(n->y_scale[i]) || !isfinite(n->y_shift[i]))
+      return false;
+  for (int i = 0; i < NI; ++i)
+    if (!isfinite(n->x_scale[i]) || !isfinite(n->x_shift[i])) return false;
+  return true;
+}
+
+int grad_blocks(int n) {
+  const int tiles = (n + TS - 1) / TS;
+  return tiles < MAX_GRAD_BLOCKS ? tiles : MAX_GRAD_BLOCKS;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace mlpk
+
+using namespace mlpk;
+
+extern "C" {
+
+lbm_status lbm_mlp_workspace_bytes(int32_t n, size_t* bytes) {
+  if (n < 1 || !bytes) return LBM_ERR_INVALID_ARG;
+  const int g = grad_blocks(n);
+  *bytes = align256((size_t)g * NPARAM * sizeof(float)) + align256((size_t)g * sizeof(float));
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_forward(const float* d_params, const lbm_mlp_norm* norm, const float* d_x,
+                           int32_t n, float* d_y, int32_t flags, void* hip_stream) {
+  if (!d_params || !norm || n < 0 || (n > 0 && (!d_x || !d_y)) || (flags & ~LBM_MLP_BF16))
+    return LBM_ERR_INVALID_ARG;
+  if (!norm_ok(norm)) return LBM_ERR_INVALID_ARG;
+  if (n == 0) return LBM_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const Norm nm = to_norm(norm);
+  const int nb = (n + TS - 1) / TS;
+  if (flags & LBM_MLP_BF16)
+    hipLaunchKernelGGL(k_mlp_forward<1>, dim3(nb), dim3(NT), 0, st, d_params, nm, d_x, n, d_y);
+  else
+    hipLaunchKernelGGL(k_mlp_forward<0>, dim3(nb), dim3(NT), 0, st, d_params, nm, d_x, n, d_y);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status lbm_mlp_grad(const float* d_params, const lbm_mlp_norm* norm, const float* d_x,
+                        const float* d_y, int32_t n_rows, const int32_t* d_idx, int32_t n,
+                        float* d_grad, float* d_loss, int32_t flags, void* d_workspace,
+                        size_t bytes, void* hip_stream) {
+  if (!d_params || !norm || !d_x || !d_y || !d_grad || n < 1 || n_rows < 1 ||
+      (!d_idx && n > n_rows) || (flags & ~LBM_MLP_BF16))
+    return LBM_ERR_INVALID_ARG;
+  if (!norm_ok(norm)) return LBM_ERR_INVALID_ARG;
+  size_t need;
+  lbm_mlp_workspace_bytes(n, &need);
+  if (!d_workspace || bytes < need || ((uintptr_t)d_workspace % 256) != 0)
+    return LBM_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const Norm nm = to_norm(norm);
+  const int g = grad_blocks(n);
+  float* part = (float*)d_workspace;
+  float* lpart = (float*)((char*)d_workspace + align256((size_t)g * NPARAM * sizeof(float)));
+  const float scale = 1.0f / (4.0f * (float)n);
+  if (flags & LBM_MLP_BF16)
+    hipLaunchKernelGGL(k_mlp_grad<1>, dim3(g), dim3(NT), 0, st, d_params, nm, d_x, d_y, d_idx,
+                       n, n_rows, scale, part, lpart);
+  else
+    hipLaunchKernelGGL(k_mlp_grad<0>, dim3(g), dim3(NT), 0, st, d_params, nm, d_x, d_y, d_idx,
+                       n, n_rows, scale, part, lpart);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, st, part, lpart, g,
+                     scale, d_grad, d_loss);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status lbm_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t t,
+                        float lr, float beta1, float beta2, float eps, void* hip_stream) {
+  if (!d_params || !d_m || !d_v || !d_grad || t < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f) ||
+      !(beta1 < 1.0f) || !(beta2 >= 0.0f) || !(beta2 < 1.0f) || !(eps > 0.0f))
+    return LBM_ERR_INVALID_ARG;
+  const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+  const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+  hipLaunchKernelGGL(k_mlp_adam, dim3((NPARAM + 255) / 256), dim3(256), 0,
+                     (hipStream_t)hip_stream, d_params, d_m, d_v, d_grad, lr, beta1, beta2, eps,
+                     bc1, bc2);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status lbm_mlp_train_step(float* d_params, float* d_m, float* d_v, int64_t t, float lr,
+                              const lbm_mlp_norm* norm, const float* d_x, const float* d_y,
+                              int32_t n_rows, const int32_t* d_idx, int32_t n, float* d_grad,
+                              float* d_loss, int32_t flags, void* d_workspace, size_t bytes,
+                              void* hip_stream) {
+  if (!d_m || !d_v || t < 1 || !(lr >= 0.0f)) return LBM_ERR_INVALID_ARG;
+  lbm_status s = lbm_mlp_grad(d_params, norm, d_x, d_y, n_rows, d_idx, n, d_grad, d_loss, flags,
+                              d_workspace, bytes, hip_stream);
+  if (s != LBM_OK) return s;
+  return lbm_mlp_adam(d_params, d_m, d_v, d_grad, t, lr, 0.9f, 0.999f, 1e-8f, hip_stream);
+}
+
+}  // extern "C"

@@ -60,3 +60,20 @@ def spinodal(nx: int, ny: int, rho_mean: float, amplitude: float = 0.01,
 
 def uniform(nx: int, ny: int, rho: float) -> np.ndarray:
     return np.full((ny, nx), float(rho))
+
+
+MLP_LAYER_SIZES = ((4, 128), (128, 128), (128, 128), (128, 4))
+
+
+def mlp_initial_params(seed: int) -> np.ndarray:
+    """Initial surrogate parameters as one float32 vector: per layer the
+    n_in x n_out weights (input-major) drawn from
+    U(-sqrt(6 / n_in), sqrt(6 / n_in)) / 2, then n_out zero biases;
+    numpy default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n_in, n_out in MLP_LAYER_SIZES:
+        lim = 0.5 * np.sqrt(6.0 / n_in)
+        parts.append(rng.uniform(-lim, lim, size=n_in * n_out))
+        parts.append(np.zeros(n_out))
+    return np.concatenate(parts).astype(np.float32)

@@ -31,8 +31,13 @@ EXPORTED_SYMBOLS = [
     "lbm_eos_critical", "lbm_maxwell", "lbm_sigma_li_theory", "lbm_fe_planar_theory",
     "lbm_match_p_to_fe",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_state",
-    "lbm_batch_observe", "lbm_batch_destroy",
+    "lbm_batch_observe", "lbm_batch_destroy", "lbm_batch_set_limit",
+    "lbm_mlp_forward", "lbm_mlp_workspace_bytes", "lbm_mlp_grad", "lbm_mlp_adam",
+    "lbm_mlp_train_step",
 ]
+
+MLP_NPARAMS = 34180
+MLP_BF16 = 1
 
 
 class LbmError(RuntimeError):
@@ -54,6 +59,26 @@ class Params(ctypes.Structure):
                 ("rho_ref", ctypes.c_double),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("kernel_flags", ctypes.c_uint32), ("reserved1", ctypes.c_int32)]
+
+
+class MlpNorm(ctypes.Structure):
+    _fields_ = [("x_shift", ctypes.c_float * 4), ("x_scale", ctypes.c_float * 4),
+                ("y_shift", ctypes.c_float * 4), ("y_scale", ctypes.c_float * 4)]
+
+    @classmethod
+    def make(cls, x_shift, x_scale, y_shift, y_scale) -> "MlpNorm":
+        n = cls()
+        for name, v in (("x_shift", x_shift), ("x_scale", x_scale), ("y_shift", y_shift),
+                        ("y_scale", y_scale)):
+            arr = getattr(n, name)
+            for i in range(4):
+                arr[i] = float(v[i])
+        return n
+
+    def as_dict(self) -> dict:
+        import numpy as np
+        return {k: np.array(list(getattr(self, k)), dtype=np.float64)
+                for k, _ in self._fields_}
 
 
 class Obs(ctypes.Structure):
@@ -109,6 +134,15 @@ def lib():
         L.lbm_batch_observe.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(Obs), vp, vp, vp]
         L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_batch_set_limit.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
+        NP = ctypes.POINTER(MlpNorm)
+        i32, f32 = ctypes.c_int32, ctypes.c_float
+        L.lbm_mlp_forward.argtypes = [vp, NP, vp, i32, vp, i32, vp]
+        L.lbm_mlp_workspace_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+        L.lbm_mlp_grad.argtypes = [vp, NP, vp, vp, i32, vp, i32, vp, vp, i32, vp, sz, vp]
+        L.lbm_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64, f32, f32, f32, f32, vp]
+        L.lbm_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int64, f32, NP, vp, vp, i32, vp,
+                                         i32, vp, vp, i32, vp, sz, vp]
         for name in EXPORTED_SYMBOLS:
             if name != "lbm_status_string":
                 getattr(L, name).restype = ctypes.c_int
@@ -335,6 +369,10 @@ class Batch:
                                    ctypes.byref(done)), "lbm_batch_run")
         return done.value
 
+    def set_limit(self, i: int, max_steps: int):
+        """Step limit of problem i (see lbm_batch_set_limit)."""
+        _check(lib().lbm_batch_set_limit(self._h, int(i), int(max_steps)), "lbm_batch_set_limit")
+
     def state(self):
         """(state, steps, du, flags) lists."""
         n = self.n
@@ -374,3 +412,145 @@ class Batch:
 
 def mlups(nodes: int, steps: int, seconds: float) -> float:
     return nodes * steps / seconds / 1e6 if seconds > 0 else math.nan
+
+
+# ---- calibration surrogate ------------------------------------------------------
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_ptr(stream):
+    return ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+
+
+def mlp_forward(params, norm: MlpNorm, x, bf16: bool = True, stream=None):
+    """Predictions (n, 4) float32 device tensor for features x (n, 4)."""
+    import torch
+    assert params.dtype == torch.float32 and params.numel() == MLP_NPARAMS
+    assert x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 4
+    y = torch.empty_like(x)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    _check(lib().lbm_mlp_forward(_ptr(params), ctypes.byref(norm), _ptr(x), int(x.shape[0]),
+                                 _ptr(y), MLP_BF16 if bf16 else 0, _stream_ptr(st)),
+           "lbm_mlp_forward")
+    return y
+
+
+def mlp_workspace(n: int, device):
+    import torch
+    nbytes = ctypes.c_size_t()
+    _check(lib().lbm_mlp_workspace_bytes(int(n), ctypes.byref(nbytes)), "lbm_mlp_workspace_bytes")
+    return torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+
+
+def mlp_grad(params, norm: MlpNorm, x, y, idx=None, n=None, bf16: bool = True, stream=None,
+             workspace=None):
+    """(loss tensor (1,), gradient tensor (MLP_NPARAMS,)) over the rows idx
+    (int32 device tensor) of (x, y), or over the first n rows."""
+    import torch
+    dev = x.device
+    nrows = int(x.shape[0])
+    if n is None:
+        n = int(idx.numel()) if idx is not None else nrows
+    ws = workspace if workspace is not None else mlp_workspace(n, dev)
+    grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(lib().lbm_mlp_grad(_ptr(params), ctypes.byref(norm), _ptr(x), _ptr(y), nrows,
+                              _ptr(idx), int(n), _ptr(grad), _ptr(loss),
+                              MLP_BF16 if bf16 else 0, _ptr(ws), ws.numel(), _stream_ptr(st)),
+           "lbm_mlp_grad")
+    return loss, grad
+
+
+def mlp_adam(params, m, v, grad, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+             stream=None):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(params.device)
+    _check(lib().lbm_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(t), float(lr),
+                              float(beta1), float(beta2), float(eps), _stream_ptr(st)),
+           "lbm_mlp_adam")
+
+
+class Surrogate:
+    """The calibration surrogate's parameters, Adam state and normalisation,
+    trained and evaluated by the library's kernels.  Inputs are tuples
+    (model, Tr, w, kappa); outputs (rho_l, rho_v, sigma, W)."""
+
+    # fixed input map: model in {0, 1}, Tr in [0.5, 0.95], w in [2, 8],
+    # kappa in [0.5, 2] all sent to [-1, 1]
+    X_LO = (0.0, 0.5, 2.0, 0.5)
+    X_HI = (1.0, 0.95, 8.0, 2.0)
+
+    def __init__(self, params0, device=None, bf16: bool = True):
+        import numpy as np
+        import torch
+        dev = device if device is not None else torch.device("cuda:0")
+        self.device = dev
+        self.bf16 = bf16
+        p0 = np.asarray(params0, dtype=np.float32)
+        assert p0.size == MLP_NPARAMS
+        self.params = torch.from_numpy(p0.copy()).to(dev)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        lo, hi = np.array(self.X_LO), np.array(self.X_HI)
+        self.x_shift = 0.5 * (lo + hi)
+        self.x_scale = 2.0 / (hi - lo)
+        self.norm = MlpNorm.make(self.x_shift, self.x_scale, [0.0] * 4, [1.0] * 4)
+
+    def set_target_scaling(self, y):
+        """Output normalisation from training targets: mean and standard
+        deviation of log y per output."""
+        import numpy as np
+        ly = np.log(np.asarray(y, dtype=np.float64))
+        sd = ly.std(axis=0)
+        sd[sd == 0] = 1.0
+        self.norm = MlpNorm.make(self.x_shift, self.x_scale, ly.mean(axis=0), sd)
+
+    def fit(self, x, y, epochs: int, batch: int = 256, lr: float = 2e-3, seed: int = 0,
+            lr_final: float | None = None):
+        """Adam on mini-batches drawn without replacement each epoch
+        (numpy default_rng(seed) permutations); returns per-epoch mean
+        loss (host list)."""
+        import numpy as np
+        import torch
+        xs = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(self.device)
+        ys = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(self.device)
+        n = xs.shape[0]
+        rng = np.random.default_rng(seed)
+        ws = mlp_workspace(min(batch, n), self.device)
+        grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=self.device)
+        nb = (n + batch - 1) // batch
+        # one loss slot per step, written by the kernels, read once at the end
+        lbuf = torch.empty(epochs * nb, dtype=torch.float32, device=self.device)
+        st = torch.cuda.current_stream(self.device)
+        flags = MLP_BF16 if self.bf16 else 0
+        L = lib()
+        perms = torch.from_numpy(
+            np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)).to(self.device)
+        for e in range(epochs):
+            if lr_final is not None and epochs > 1:
+                lr_e = lr * (lr_final / lr) ** (e / (epochs - 1))
+            else:
+                lr_e = lr
+            for b in range(nb):
+                idx = perms[e, b * batch:(b + 1) * batch]
+                self.t += 1
+                _check(L.lbm_mlp_train_step(_ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                            self.t, float(lr_e), ctypes.byref(self.norm),
+                                            _ptr(xs), _ptr(ys), int(n), _ptr(idx),
+                                            int(idx.numel()), _ptr(grad), _ptr(lbuf[e * nb + b:]),
+                                            flags, _ptr(ws), ws.numel(), _stream_ptr(st)),
+                       "lbm_mlp_train_step")
+        per_step = lbuf.cpu().numpy().reshape(epochs, nb)
+        sizes = np.array([min(batch, n - b * batch) for b in range(nb)], dtype=np.float64)
+        return list(per_step @ sizes / n)
+
+    def predict(self, x):
+        """Host (n, 4) float64 predictions."""
+        import numpy as np
+        import torch
+        xs = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(self.device)
+        return mlp_forward(self.params, self.norm, xs, self.bf16).cpu().numpy().astype(np.float64)
+

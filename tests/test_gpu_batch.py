@@ -155,3 +155,25 @@ def test_autotuned_launch_keeps_parity(model):
     _, (rho, _, _) = sim.observe(fields=True)
     rref, _ = oracle_rho(cfg, r0, 60)
     assert rel(rho.cpu().numpy(), rref) < FP64_RTOL
+
+
+def test_step_limit_retires_and_resumes():
+    """A per-problem step limit retires that problem at a check; raising the
+    limit resumes it from its state; both histories equal the oracle."""
+    cases = mixed_cases()[:3]
+    b = lbm.Batch([c for c, _ in cases], [to_dev(r) for _, r in cases])
+    b.set_limit(1, 80)
+    b.set_limit(2, 0)  # retires before its first step
+    b.run(check_every=40, du_tol=0.0, max_steps=160)
+    st, nsteps, _, _ = b.state()
+    assert st == [lbm.BATCH_MAXSTEPS] * 3 and nsteps == [160, 80, 0]
+    b.set_limit(1, 120)
+    b.set_limit(2, 40)
+    b.run(check_every=40, du_tol=0.0, max_steps=200)
+    st, nsteps, _, _ = b.state()
+    assert nsteps == [160, 120, 40], nsteps
+    for i, (c, r0) in enumerate(cases):
+        _, (rho, _, _) = b.observe(i, fields=True)
+        rref, _ = oracle_rho(c, r0, nsteps[i])
+        assert rel(rho.cpu().numpy(), rref) < FP64_RTOL, i
+    b.close()
