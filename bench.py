@@ -158,6 +158,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-vdw", action="store_true",
+                    help="skip the van der Waals Tr = 0.7 variant lines")
+    ap.add_argument("--no-calibration", action="store_true",
+                    help="skip the surrogate-seeded vs plain batched calibration leg")
+    ap.add_argument("--calib-train", type=int, default=2000)
+    ap.add_argument("--calib-held", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -204,6 +210,34 @@ def main():
             print(f"# {mname} {pname}: {ms:.4f} ms/step, {N * K / secs / 1e6:.0f} MLUPS, "
                   f"flags {obs['flags']}", file=sys.stderr, flush=True)
 
+    variants_vdw = None
+    if not args.no_vdw and args.workload != "vdw-spinodal":
+        vf, vrho0, vdesc = workload("vdw-spinodal", args.n)
+        vr = torch.from_numpy(vrho0).to(dev)
+        variants_vdw = {"workload": vdesc}
+        for pname, prec in precs:
+            for mname, model in (("P", lbm.MODEL_P), ("FE", lbm.MODEL_FE)):
+                secs, obs = time_variant(vf(model, prec), vr, K, W)
+                ms = secs * 1e3 / K
+                variants_vdw[f"{mname}_{pname}"] = dict(
+                    mlups=N * K / secs / 1e6, ms_per_step=ms, flags=int(obs["flags"]),
+                    finite=bool(math.isfinite(obs["mass"])))
+                print(f"# vdW {mname} {pname}: {ms:.4f} ms/step, flags {obs['flags']}",
+                      file=sys.stderr, flush=True)
+        del vr
+        torch.cuda.empty_cache()
+
+    calib = None
+    if not args.no_calibration:
+        from paper_2403_11167_amd import calibration
+        try:
+            calib = calibration.benchmark(
+                n_train=args.calib_train, n_held=args.calib_held,
+                log=lambda m: print(f"# calibration: {m}", file=sys.stderr, flush=True))
+        except Exception as e:  # report, do not lose the step measurement
+            calib = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
+
     t_p = variants["P_fp64"]["ms_per_step"]
     t_fe = variants["FE_fp64"]["ms_per_step"]
     ms_per_step = t_p + t_fe
@@ -224,7 +258,7 @@ def main():
         cpu = cpu_baseline(cfg_factory, rho0, args.cpu_seconds)
 
     line = {
-        "metric": "MLUPS (4096^2 D2Q9 multiphase step, both models) + HBM GB/s % peak",
+        "metric": "MLUPS + HBM GB/s % peak (4096\u00b2 D2Q9); calibration runs/sec, surrogate vs plain",
         "value": value,
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -243,6 +277,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
+        "variants_vdw_spinodal": variants_vdw,
+        "calibration": calib,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

@@ -99,7 +99,9 @@ typedef struct {
   /* Launch shape; 0 selects the tuned default (see lbm_autotune).  Results
      do not depend on these, only the speed does. */
   int32_t tile_x;       /* columns per workgroup strip: 0, 64 or 256         */
-  int32_t tile_y;       /* rows per workgroup segment: 0 or 1 .. 1024        */
+  int32_t tile_y;       /* rows per workgroup segment: 1 .. 1024, or 0: set at
+                           the first step so that the tiles fill whole rounds
+                           of resident workgroups (at least 16 rows)        */
   int32_t kernel_flags; /* 0, or LBM_KF_SET | any of the LBM_KF_* below      */
   int32_t reserved1;    /* must be 0                                        */
 } lbm_params;
@@ -224,6 +226,12 @@ lbm_status lbm_batch_observe(lbm_batch* b, int32_t i, int32_t cx, int32_t cy, lb
 lbm_status lbm_batch_destroy(lbm_batch* b);
 
 /* ---- host thermodynamics (no device work) ------------------------------ */
+
+/* Pressure and dp/drho of the EOS at density rho (Eq. 28 for
+ * Carnahan-Starling; van der Waals p = rho R T/(1 - b rho) - a rho^2).
+ * LBM_ERR_EOS_DOMAIN outside 0 < rho < rho_max. */
+lbm_status lbm_eos_eval(int32_t eos, double a, double b, double R, double T, double rho,
+                        double* p, double* dp_drho);
 
 /* Critical point of the EOS: van der Waals in closed form, Carnahan-Starling
  * from p' = p'' = 0 (Sec. 3).  Outputs may not be NULL. */

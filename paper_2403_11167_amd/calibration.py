@@ -109,6 +109,23 @@ def droplet_rho0(L: int, rl: float, rv: float, W: float):
     return inputs.droplet(L, L, rl, rv, radius=L / 5.0, width=max(W, 1.0))
 
 
+def laplace_densities(cfg: lbm.Config, rl: float, rv: float, sigma: float, R: float):
+    """Bulk densities (inside, outside) of a droplet of radius R in
+    equilibrium, to first order about the planar coexistence densities: the
+    bulk pressures differ by sigma / R (Laplace's law, Sec. 5.2) and the
+    chemical potential (mu_b, Eq. 29, d mu = dp / rho) is equal on both
+    sides, so dp_in / rho_l = dp_out / rho_v.  Exact to first order for the
+    thermodynamically consistent free-energy model; for the pseudopotential
+    model it is the estimate of its Maxwell-close coexistence."""
+    _, dpl = lbm.eos_eval(cfg.eos, cfg.a, cfg.b, cfg.R, cfg.T, rl)
+    _, dpv = lbm.eos_eval(cfg.eos, cfg.a, cfg.b, cfg.R, cfg.T, rv)
+    if not (dpl > 0 and dpv > 0):
+        raise ValueError("densities on an unstable branch")
+    dp_v = (sigma / R) * rv / (rl - rv)
+    dp_l = (sigma / R) * rl / (rl - rv)
+    return rl + dp_l / dpl, rv + dp_v / dpv
+
+
 def flat_labels(rho: np.ndarray):
     """(rho_l, rho_v, W) of a flat-interface equilibrium (rows identical)."""
     prof = rho.mean(axis=0)
@@ -136,13 +153,23 @@ def build_problems(tuples, sizes, precision, guesses=None):
     (None: plain guesses)."""
     cfgs, rho0s, meta = [], [], []
     for k, (t, size) in enumerate(zip(tuples, sizes)):
-        rl, rv, W = guesses[k] if guesses is not None else initial_guess(t)
+        g = guesses[k] if guesses is not None else initial_guess(t)
+        rl, rv, W = g[:3]
         fx, fy, L = _shape(size)
         cfgs.append(model_config(t, fx, fy, precision))
         rho0s.append(flat_rho0(fx, fy, rl, rv, W))
         meta.append((k, "flat"))
-        cfgs.append(model_config(t, L, L, precision))
-        rho0s.append(droplet_rho0(L, rl, rv, W))
+        cd = model_config(t, L, L, precision)
+        dl, dv = rl, rv
+        if len(g) > 3 and g[3] > 0:
+            try:
+                dl, dv = laplace_densities(cd, rl, rv, g[3], L / 5.0)
+            except (ValueError, lbm.LbmError):
+                dl, dv = rl, rv
+            if not (0 < dv < dl):
+                dl, dv = rl, rv
+        cfgs.append(cd)
+        rho0s.append(droplet_rho0(L, dl, dv, W))
         meta.append((k, "droplet"))
     return cfgs, rho0s, meta
 
@@ -298,9 +325,12 @@ def training_set(n_tuples: int, seed: int, size=(64, 8, 128), **kw):
     return features(tuples)[m], targets(labels)[m], info
 
 
-def seeded_guesses(pred):
-    """Initial-profile parameters (rho_l, rho_v, W) from surrogate
-    predictions (n x 4: rho_l, rho_v, sigma, W)."""
+def seeded_guesses(pred, laplace: bool = True):
+    """Initial-profile parameters (rho_l, rho_v, W[, sigma]) from surrogate
+    predictions (n x 4: rho_l, rho_v, sigma, W); with sigma, droplets start
+    from the Laplace-shifted bulk densities (laplace_densities)."""
+    if laplace:
+        return [(float(p[0]), float(p[1]), float(p[3]), float(p[2])) for p in pred]
     return [(float(p[0]), float(p[1]), float(p[3])) for p in pred]
 
 
@@ -311,4 +341,73 @@ def compare(labels_a, labels_b):
     ya, yb = targets(labels_a)[m], targets(labels_b)[m]
     rel = np.abs(yb / ya - 1)
     return {k: rel[:, i] for i, k in enumerate(("rho_l", "rho_v", "sigma", "W"))}, m
+
+
+def _stats(rel, tol):
+    return dict(median=float(np.median(rel)), p95=float(np.percentile(rel, 95)),
+                max=float(np.max(rel)), frac_within=float(np.mean(rel <= tol)), tol=tol)
+
+
+TOLERANCES = dict(rho_l=0.01, rho_v=0.01, sigma=0.03, W=0.03)
+
+
+def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_held: int = 6,
+              epochs: int = 400, crossings: float = 8.0, max_steps: int = 200000,
+              train_size=(64, 8, 128), log=None):
+    """Surrogate-seeded against plain calibration on held-out tuples.
+
+    Trains the surrogate on equilibria of n_train sampled tuples (small
+    lattices), then calibrates n_held held-out tuples (one flat and one
+    droplet lattice each, L drawn from 64..512) twice: plain (Maxwell
+    densities, width w, run to the convergence rule) and surrogate-seeded
+    (run_seeded_calibration).  Returns a JSON-ready dict with wall times,
+    converged tuples per second and the errors of the seeded labels and of
+    the bare predictions against the plain labels."""
+    import time
+
+    import torch
+    say = log or (lambda *a: None)
+    t0 = time.perf_counter()
+    x, y, info_t = training_set(n_train, seed_train, size=train_size, max_steps=max_steps)
+    gen_s = time.perf_counter() - t0
+    say(f"training set: {len(x)} valid of {n_train} tuples in {gen_s:.1f} s")
+    sur = lbm.Surrogate(inputs.mlp_initial_params(0))
+    sur.set_target_scaling(y)
+    t1 = time.perf_counter()
+    losses = sur.fit(x, y, epochs=epochs, batch=256, lr=3e-3, seed=1, lr_final=1e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    say(f"training: {train_s:.2f} s, loss {losses[0]:.4f} -> {losses[-1]:.2e}")
+    tup = sample_tuples(n_held, seed_held)
+    sizes = sample_sizes(n_held, seed_held)
+    lab_p, inf_p = run_calibration(tup, sizes, max_steps=max_steps)
+    say(f"plain: {inf_p['seconds']:.1f} s, {inf_p['converged_units']} tuples")
+    lab_s, inf_s = run_seeded_calibration(tup, sizes, sur, max_steps=max_steps,
+                                          crossings=crossings)
+    say(f"seeded: {inf_s['seconds']:.1f} s, {inf_s['converged_units']} tuples, "
+        f"{inf_s['accepted']} accepted after verification")
+    rel, m = compare(lab_p, lab_s)
+    pred = inf_s["prediction"]
+    yp = targets(lab_p)
+    mp = valid(lab_p)
+    prel = np.abs(pred[mp] / yp[mp] - 1)
+    names = ("rho_l", "rho_v", "sigma", "W")
+    return dict(
+        held_out=dict(tuples=n_held, lattices=2 * n_held, seed=seed_held,
+                      sizes="L x L, L uniform in {64,128,256,512}; flat slab + droplet R = L/5",
+                      precision="fp32_shifted"),
+        training=dict(tuples=n_train, valid=int(len(x)), lattices=2 * n_train,
+                      size=list(train_size), generation_s=gen_s, train_s=train_s,
+                      epochs=epochs, loss_first=float(losses[0]), loss_last=float(losses[-1])),
+        plain=dict(seconds=inf_p["seconds"], tuples_converged=inf_p["converged_units"],
+                   tuples_per_s=inf_p["units_per_second"], lockstep_steps=inf_p["steps"]),
+        seeded=dict(seconds=inf_s["seconds"], tuples_converged=inf_s["converged_units"],
+                    tuples_per_s=inf_s["units_per_second"], lockstep_steps=inf_s["steps"],
+                    accepted_after_verification=inf_s["accepted"],
+                    fallback=inf_s["fallback"], verification_crossings=crossings),
+        speedup=inf_p["seconds"] / inf_s["seconds"],
+        seeded_vs_plain={k: _stats(rel[k], TOLERANCES[k]) for k in names},
+        seeded_vs_plain_tuples=int(m.sum()),
+        surrogate_vs_plain={k: _stats(prel[:, i], TOLERANCES[k]) for i, k in enumerate(names)},
+    )
 

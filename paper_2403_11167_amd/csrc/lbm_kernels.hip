@@ -179,9 +179,6 @@ __device__ __forceinline__ void st(S* p, S v) {
   if constexpr (NT & 1) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
-// Pulled deviations g_i(x, y) = g*_i(x - c_i) for one node; rm / r0 / rp are
-// the row offsets of y-1, y, y+1 and xm / x / xp the columns x-1, x, x+1
-// (periodic wrap already applied).
 // Column offset of x inside a row of the blocked layout.
 __device__ __forceinline__ int colo(int x) { return (x >> 6) * 576 + (x & 63); }
 
@@ -553,7 +550,12 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
 // Software-pipelined variant: the populations of row y+2 (interior and
 // halo columns) are loaded at the top of the iteration that collides row y
 // and only consumed one iteration later, so their memory latency overlaps
-// the psi row, the barrier and the collision in between.
+// the psi row, the barrier and the collision in between.  The interior
+// loads are issued unconditionally (lanes past the lattice edge read a valid
+// column and discard it) and after the halo loads, and the last row is
+// peeled off the loop: the wait for a row's populations can then count the
+// next row's loads as issued and leaves them in flight (a load inside a
+// branch that may be skipped would force a wait for every outstanding load).
 template <int EOS, class S, class C, int BX, int NT>
 __device__ __forceinline__ void tile_p_pipe(const S* __restrict__ src, S* __restrict__ dst,
                                             const KParams<C>& kp, unsigned* __restrict__ flags,
@@ -584,14 +586,13 @@ __device__ __forceinline__ void tile_p_pipe(const S* __restrict__ src, S* __rest
   auto rowoff = [&](int y) { return wrapi(y, ny) * kp.rowpitch; };
   auto pull_row = [&](int y, C g[9], C h[9]) {
     const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
-    if (active) pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
     if (hl) pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
+    pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
   };
   // psi row from pulled populations; returns the interior density deviation
   auto psi_row = [&](const C g[9], const C h[9], C* row) {
-    C dr = C(0);
+    C dr = sum9(g);
     if (active) {
-      dr = sum9(g);
       C rho = kp.rho_ref + dr;
       fl |= domain_flags<MODEL_P, EOS>(rho, kp);
       row[t + 1] = psi_of<EOS>(rho, kp, fl);
@@ -599,23 +600,9 @@ __device__ __forceinline__ void tile_p_pipe(const S* __restrict__ src, S* __rest
     if (hl) row[hj] = psi_of<EOS>(kp.rho_ref + sum9(h), kp, fl);
     return dr;
   };
-
-  {
-    C g[9], h[9];
-    pull_row(y0 - 1, g, h);
-    psi_row(g, h, psi_s[0]);
-    pull_row(y0, gc, h);
-    drho_c = psi_row(gc, h, psi_s[1]);
-    pull_row(y0 + 1, gn, hn);
-  }
-
-  for (int k = 0; k < ly; ++k) {
-    const int y = y0 + k;
-    C g2[9], h2[9];
-    if (k + 2 <= ly) pull_row(y + 2, g2, h2);
-    C drho_n = psi_row(gn, hn, psi_s[(k + 2) & 3]);
-    __syncthreads();
+  auto collide_row = [&](int k) {
     if (active) {
+      const int y = y0 + k;
       C v[9];
       gather(psi_s[k & 3], psi_s[(k + 1) & 3], psi_s[(k + 2) & 3], t + 1, v);
       C sx, sy;
@@ -632,6 +619,23 @@ __device__ __forceinline__ void tile_p_pipe(const S* __restrict__ src, S* __rest
 #pragma unroll
       for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)gc[i]);
     }
+  };
+
+  {
+    C g[9], h[9];
+    pull_row(y0 - 1, g, h);
+    psi_row(g, h, psi_s[0]);
+    pull_row(y0, gc, h);
+    drho_c = psi_row(gc, h, psi_s[1]);
+    pull_row(y0 + 1, gn, hn);
+  }
+
+  for (int k = 0; k < ly - 1; ++k) {
+    C g2[9], h2[9];
+    pull_row(y0 + k + 2, g2, h2);
+    C drho_n = psi_row(gn, hn, psi_s[(k + 2) & 3]);
+    __syncthreads();
+    collide_row(k);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       gc[i] = gn[i];
@@ -639,6 +643,13 @@ __device__ __forceinline__ void tile_p_pipe(const S* __restrict__ src, S* __rest
       hn[i] = h2[i];
     }
     drho_c = drho_n;
+  }
+  {
+    const int k = ly - 1;
+    C drho_n = psi_row(gn, hn, psi_s[(k + 2) & 3]);
+    __syncthreads();
+    collide_row(k);
+    (void)drho_n;
   }
   commit_flags(fl, flags, &s_flag);
 }
@@ -762,6 +773,146 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
   chk_commit<CHK>(ck, dmax, s_du);
 }
 
+// Software-pipelined free-energy tile: the populations of row y+3 are
+// loaded at the top of the iteration that collides row y and consumed (as
+// the density row y+3) one iteration later, so their latency overlaps the
+// chemical-potential row, two barriers and a collision.  Four population
+// rows are live (y .. y+3).  As in tile_p_pipe, interior loads are
+// unconditional and follow the halo loads, and the last row is peeled.
+template <int EOS, class S, class C, int BX, int NT, int CHK>
+__device__ __forceinline__ void tile_fe_pipe(const S* __restrict__ src, S* __restrict__ dst,
+                                             const KParams<C>& kp, unsigned* __restrict__ flags,
+                                             int x0, int y0, const ChkOut<C>& ck) {
+  __shared__ C rho_s[8][BX + 4];
+  __shared__ C mu_s[4][BX + 2];
+  __shared__ unsigned s_flag;
+  __shared__ double s_du[BX / 64];
+  if (threadIdx.x == 0) s_flag = 0u;
+  const int nx = kp.nx, ny = kp.ny;
+  const int w = min(BX, nx - x0);
+  const int ly = min(kp.LY, ny - y0);
+  const int t = threadIdx.x;
+  const bool active = t < w;
+  const int x = x0 + (active ? t : 0);
+  const int xm = (x == 0) ? nx - 1 : x - 1;
+  const int xp = (x == nx - 1) ? 0 : x + 1;
+  const int cm = colo(xm), c0 = colo(x), cp = colo(xp);
+  const bool hr = t < 4;
+  const int hoff = (t < 2) ? (t - 2) : (w + t - 2);
+  const int hx = wrapi(x0 + hoff, nx);
+  const int hxm = (hx == 0) ? nx - 1 : hx - 1;
+  const int hxp = (hx == nx - 1) ? 0 : hx + 1;
+  const int hcm = colo(hxm), hc0 = colo(hx), hcp = colo(hxp);
+  const int hj = hoff + 2;
+  const bool hm = t < 2;
+  const int hmj = (t == 0) ? 0 : w + 1;
+
+  unsigned fl = 0;
+  C dmax = C(0);
+  C g0[9], g1[9], g2[9], h2[9];
+  C d0 = C(0), d1 = C(0);
+
+  auto rowoff = [&](int y) { return wrapi(y, ny) * kp.rowpitch; };
+  auto pull_row = [&](int y, C g[9], C h[9]) {
+    const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
+    if (hr) pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
+    pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
+  };
+  // density deviation row into ring slot; returns the interior value
+  auto rho_row = [&](int slot, const C g[9], const C h[9]) {
+    C dr = sum9(g);
+    C* row = rho_s[slot & 7];
+    if (active) {
+      fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dr, kp);
+      row[t + 2] = dr;
+    }
+    if (hr) row[hj] = sum9(h);
+    return dr;
+  };
+  auto mu_row = [&](int rs, int ms) {
+    const C* bot = rho_s[(rs - 1) & 7];
+    const C* mid = rho_s[rs & 7];
+    const C* top = rho_s[(rs + 1) & 7];
+    C* out = mu_s[ms & 3];
+    if (active) {
+      C v[9];
+      gather(bot, mid, top, t + 2, v);
+      out[t + 1] = mu_dev<EOS>(v[0], kp) - kp.kappa * lap9(v);
+    }
+    if (hm) {
+      C v[9];
+      gather(bot, mid, top, hmj + 1, v);
+      out[hmj] = mu_dev<EOS>(v[0], kp) - kp.kappa * lap9(v);
+    }
+  };
+  auto collide_row = [&](int k) {
+    if (active) {
+      const int y = y0 + k;
+      C v[9], m[9];
+      gather(rho_s[(k + 1) & 7], rho_s[(k + 2) & 7], rho_s[(k + 3) & 7], t + 2, v);
+      gather(mu_s[k & 3], mu_s[(k + 1) & 3], mu_s[(k + 2) & 3], t + 1, m);
+      C grx, gry, gmx, gmy;
+      grad_sum(v, grx, gry);  // Eq. 24 gradient of rho
+      grad_sum(m, gmx, gmy);  // Eq. 24 gradient of mu
+      C rho = kp.rho_ref + d0;
+      C Fx = -rho * gmx + kp.fx;  // F = -rho grad(mu)
+      C Fy = -rho * gmy + kp.fy;
+      C ux, uy;
+      collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
+      chk_node<CHK>(ck, y * nx + x, ux, uy, dmax);
+      const int off = y * kp.rowpitch + c0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)g0[i]);
+    }
+  };
+
+  // rho slots: row y0-2+r -> slot r.  mu slots: row y0-1+q -> slot q.
+  {
+    C tmp[9], th[9];
+    pull_row(y0 - 2, tmp, th);
+    rho_row(0, tmp, th);
+    pull_row(y0 - 1, tmp, th);
+    rho_row(1, tmp, th);
+    pull_row(y0, g0, th);
+    d0 = rho_row(2, g0, th);
+    pull_row(y0 + 1, g1, th);
+    d1 = rho_row(3, g1, th);
+    pull_row(y0 + 2, g2, h2);
+  }
+  __syncthreads();
+  mu_row(1, 0);  // row y0-1
+  mu_row(2, 1);  // row y0
+
+  for (int k = 0; k < ly - 1; ++k) {
+    C g3[9], h3[9];
+    pull_row(y0 + k + 3, g3, h3);
+    C d2 = rho_row(k + 4, g2, h2);  // row y+2
+    __syncthreads();
+    mu_row(k + 3, k + 2);  // row y+1
+    __syncthreads();
+    collide_row(k);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      g0[i] = g1[i];
+      g1[i] = g2[i];
+      g2[i] = g3[i];
+      h2[i] = h3[i];
+    }
+    d0 = d1;
+    d1 = d2;
+  }
+  {
+    const int k = ly - 1;
+    rho_row(k + 4, g2, h2);
+    __syncthreads();
+    mu_row(k + 3, k + 2);
+    __syncthreads();
+    collide_row(k);
+  }
+  commit_flags(fl, flags, &s_flag);
+  chk_commit<CHK>(ck, dmax, s_du);
+}
+
 // ---- single-lattice step kernels --------------------------------------------
 template <int EOS, class S, class C, int BX, int NT, int WPE>
 __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
@@ -788,6 +939,16 @@ void k_step_fe(const S* __restrict__ src, S* __restrict__ dst, const KParams<C> 
   const int tile = tile_index(kp.xcd_remap);
   tile_fe<EOS, S, C, BX, NT, 0>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
                                 (tile / kp.nstrips) * kp.LY, ChkOut<C>{nullptr, nullptr, nullptr});
+}
+
+template <int EOS, class S, class C, int BX, int NT, int WPE>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_step_fe_pipe(const S* __restrict__ src, S* __restrict__ dst, const KParams<C> kp,
+                    unsigned* __restrict__ flags) {
+  const int tile = tile_index(kp.xcd_remap);
+  tile_fe_pipe<EOS, S, C, BX, NT, 0>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
+                                     (tile / kp.nstrips) * kp.LY,
+                                     ChkOut<C>{nullptr, nullptr, nullptr});
 }
 
 // Occupancy targets (waves per SIMD) of the register-capped variants.
@@ -1241,7 +1402,8 @@ struct LaunchCfg {
   int ly;    // segment height
   int nt;    // 1: non-temporal population stores
   int wpe;   // 1: register-capped kernel variant
-  int pipe;  // 1: pipelined row loop (pseudopotential, FP64)
+  int pipe;  // 1: pipelined row loop (pseudopotential)
+  int auto_ly;  // 1: segment height set at the first launch from occupancy
 };
 
 }  // namespace
@@ -1264,11 +1426,15 @@ struct lbm_ctx {
 namespace {
 
 // Launch-shape resolution: explicit fields of lbm_params first, then the
-// LBM_TILE_X / LBM_LY / LBM_NT / LBM_WPE / LBM_PIPE environment overrides
-// (tuning experiments), then defaults measured on MI355X (4096^2 lattices:
-// 256-column strips, non-temporal stores, register-capped kernels, the
-// pipelined pseudopotential kernel in FP64, 32-row segments in FP64 and
-// 16-row segments in FP32; 64-column strips for lattices narrower than 256).
+// LBM_TILE_X / LBM_LY / LBM_NT / LBM_WPE / LBM_PIPE / LBM_ROUNDS environment
+// overrides (tuning experiments), then defaults measured on MI355X (4096^2
+// lattices: 256-column strips, non-temporal stores, the pipelined
+// pseudopotential kernel without a register cap, the register-capped
+// free-energy kernel, pipelined in FP32; 64-column strips for lattices
+// narrower than 256).  Without an explicit
+// segment height, a single lattice gets one chosen at its first launch so
+// that all tiles run as one round of resident workgroups (see tune_ly); the
+// fallback here (batches) aims at a few thousand tiles.
 LaunchCfg resolve_launch(const lbm_params* p) {
   const bool fp64 = p->precision == LBM_FP64;
   LaunchCfg lc{};
@@ -1281,12 +1447,14 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     lc.pipe = (kf & LBM_KF_PIPELINE) ? 1 : 0;
   } else {
     lc.nt = env_int("LBM_NT", 1) ? 1 : 0;
-    lc.wpe = env_int("LBM_WPE", 1) ? 1 : 0;
-    lc.pipe = env_int("LBM_PIPE", fp64 ? 1 : 0) ? 1 : 0;
+    lc.wpe = env_int("LBM_WPE", p->model == LBM_MODEL_P ? 0 : 1) ? 1 : 0;
+    // pipelined row loop: pseudopotential always; free energy in FP32 only
+    // (in FP64 its four live population rows cost a wave of occupancy)
+    lc.pipe = env_int("LBM_PIPE", (p->model == LBM_MODEL_P || !fp64) ? 1 : 0) ? 1 : 0;
   }
-  if (p->model != LBM_MODEL_P) lc.pipe = 0;
   int nstrips = (p->nx + lc.bx - 1) / lc.bx;
   int LY = p->tile_y ? p->tile_y : env_int("LBM_LY", 0);
+  lc.auto_ly = (LY <= 0 && env_int("LBM_ROUNDS", 1) > 0) ? 1 : 0;
   if (LY <= 0) {
     // enough tiles to fill 256 CUs several times over, segments of at
     // least 8 rows so the two halo rows stay a small overhead
@@ -1324,16 +1492,51 @@ void apply_launch(lbm_ctx* c) {
   c->kf.xcd_remap = c->xcd_remap;
 }
 
+// Segment height from occupancy: with R workgroups resident on the device
+// (the kernel's blocks per CU times the CU count) the lattice is cut into
+// at most k R tiles of equal height, so one launch is k full rounds of
+// workgroups with no partly filled tail round; segments stay at least 16
+// rows so the halo rows remain a small overhead.
+template <class K>
+void tune_ly(lbm_ctx* c, K kernel, int bx) {
+  c->lc.auto_ly = 0;
+  int blocks = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, bx, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      blocks < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return;  // keep the fallback height
+  }
+  // measured on 4096^2: the free-energy kernel is fastest with one round,
+  // the pseudopotential kernel with about three
+  const int rounds = env_int("LBM_ROUNDS", c->p.model == LBM_MODEL_P ? 3 : 1);
+  const int resident = blocks * cus * std::max(1, rounds);
+  const int segs = std::max(1, resident / c->nstrips);
+  int LY = (c->p.ny + segs - 1) / segs;
+  LY = std::max(LY, std::min(16, c->p.ny));
+  c->lc.ly = std::min(LY, c->p.ny);
+  apply_launch(c);
+}
+
 template <int MODEL, int EOS, class S, class C, int BX, int NT, int WPE>
 void launch_step_w(lbm_ctx* c, const KParams<C>& kp) {
+  if (c->lc.auto_ly) {
+    if (MODEL == MODEL_P && c->lc.pipe) tune_ly(c, k_step_p_pipe<EOS, S, C, BX, NT, WPE>, BX);
+    else if (MODEL == MODEL_P) tune_ly(c, k_step_p<EOS, S, C, BX, NT, WPE>, BX);
+    else if (c->lc.pipe) tune_ly(c, k_step_fe_pipe<EOS, S, C, BX, NT, WPE>, BX);
+    else tune_ly(c, k_step_fe<EOS, S, C, BX, NT, WPE>, BX);
+  }
   const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
   S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
   unsigned* flags = (unsigned*)(c->ws + c->L.flags);
   dim3 grid(c->nstrips * c->nseg), block(BX);
-  if (MODEL == MODEL_P && c->lc.pipe && sizeof(C) == 8)
+  if (MODEL == MODEL_P && c->lc.pipe)
     hipLaunchKernelGGL((k_step_p_pipe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
   else if (MODEL == MODEL_P)
     hipLaunchKernelGGL((k_step_p<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+  else if (c->lc.pipe)
+    hipLaunchKernelGGL((k_step_fe_pipe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
   else
     hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
   c->cur ^= 1;
@@ -1625,12 +1828,16 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
   if ((st = read_host(d_rho0, (size_t)p->nx * p->ny, stream, h)) != LBM_OK) return st;
   const bool fp64 = p->precision == LBM_FP64;
   std::vector<int> bxs = {64, 256};
-  std::vector<int> lys = {8, 16, 32, 64};
+  // tile_y 0: the occupancy-derived one-round segment height
+  std::vector<int> lys = {0, 8, 16, 32, 64};
   std::vector<unsigned> kfs = {LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_REGCAP,
                                LBM_KF_SET | LBM_KF_NT_STORE,
                                LBM_KF_SET | LBM_KF_REGCAP};
-  if (fp64 && p->model == LBM_MODEL_P)
+  if (p->model == LBM_MODEL_P) {
+    kfs.push_back(LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_PIPELINE);
     kfs.push_back(LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_REGCAP | LBM_KF_PIPELINE);
+  }
+  (void)fp64;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBM_ERR_HIP;
   double best_t = INFINITY;

@@ -264,6 +264,16 @@ bool p_theory_unit(const Eos& E, double eps, double* width1, double* I1) {
 
 extern "C" {
 
+lbm_status lbm_eos_eval(int32_t eos, double a, double b, double R, double T, double rho,
+                        double* p, double* dp_drho) {
+  if (!p || !dp_drho || !ok_eos(eos, a, b, R) || !(T > 0.0)) return LBM_ERR_INVALID_ARG;
+  Eos E{eos, a, b, R, T};
+  if (!(rho > 0.0) || !(rho < E.rho_max())) return LBM_ERR_EOS_DOMAIN;
+  *p = E.p(rho);
+  *dp_drho = E.dp(rho);
+  return LBM_OK;
+}
+
 lbm_status lbm_eos_critical(int32_t eos, double a, double b, double R, double* Tc,
                             double* rho_c, double* p_c) {
   if (!Tc || !rho_c || !p_c || !ok_eos(eos, a, b, R)) return LBM_ERR_INVALID_ARG;

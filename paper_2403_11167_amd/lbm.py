@@ -28,7 +28,7 @@ KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE = 0x80000000, 1, 2, 4
 EXPORTED_SYMBOLS = [
     "lbm_status_string", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe",
     "lbm_get_populations", "lbm_set_populations", "lbm_destroy", "lbm_autotune",
-    "lbm_eos_critical", "lbm_maxwell", "lbm_sigma_li_theory", "lbm_fe_planar_theory",
+    "lbm_eos_eval", "lbm_eos_critical", "lbm_maxwell", "lbm_sigma_li_theory", "lbm_fe_planar_theory",
     "lbm_match_p_to_fe",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_state",
     "lbm_batch_observe", "lbm_batch_destroy", "lbm_batch_set_limit",
@@ -117,6 +117,7 @@ def lib():
         L.lbm_get_populations.argtypes = [vp, vp]
         L.lbm_set_populations.argtypes = [vp, vp]
         L.lbm_destroy.argtypes = [vp]
+        L.lbm_eos_eval.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 5 + [D] * 2
         L.lbm_eos_critical.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 3 + [D] * 3
         L.lbm_maxwell.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 4 + [D] * 3
         L.lbm_sigma_li_theory.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 4 + [D] * 2
@@ -162,6 +163,14 @@ def _check(st: int, what: str):
 # ---- host thermodynamics ---------------------------------------------------
 def _outs(n):
     return [ctypes.c_double() for _ in range(n)]
+
+
+def eos_eval(eos: int, a: float, b: float, R: float, T: float, rho: float):
+    """(p, dp/drho) of the EOS at rho."""
+    o = _outs(2)
+    _check(lib().lbm_eos_eval(eos, a, b, R, T, rho, *[ctypes.byref(v) for v in o]),
+           "lbm_eos_eval")
+    return tuple(v.value for v in o)
 
 
 def eos_critical(eos: int, a: float, b: float, R: float):

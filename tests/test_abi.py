@@ -112,6 +112,17 @@ def test_maxwell(eos, a, b, Tr):
         assert math.isclose(g, r, rel_tol=1e-11)
 
 
+@pytest.mark.parametrize("eos,a,b", [(lbm.EOS_CS, 0.25, 4.0), (lbm.EOS_VDW, 9 / 49, 2 / 21)])
+def test_eos_eval(eos, a, b):
+    T = 0.8 * th.critical(eos, a, b, 1.0)[0]
+    for rho in (0.01, 0.1, 0.3, 0.9 * (4 / b if eos == lbm.EOS_CS else 1 / b)):
+        p, dp = lbm.eos_eval(eos, a, b, 1.0, T, rho)
+        assert math.isclose(p, th.pressure(eos, rho, a, b, 1.0, T), rel_tol=1e-13, abs_tol=1e-15)
+        assert math.isclose(dp, th.dpressure(eos, rho, a, b, 1.0, T), rel_tol=1e-11, abs_tol=1e-13)
+    with pytest.raises(lbm.LbmError):
+        lbm.eos_eval(eos, a, b, 1.0, T, -0.1)
+
+
 def test_maxwell_above_critical_is_rejected():
     with pytest.raises(lbm.LbmError):
         lbm.maxwell(lbm.EOS_VDW, 9 / 49, 2 / 21, 1.0, 0.6)

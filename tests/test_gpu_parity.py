@@ -311,20 +311,26 @@ def test_coexistence_densities_fp64_and_fp32(model):
 
 # ------------------------------------------------------------------ throughput lattice
 @pytest.mark.parametrize("model", ["P", "FE"])
-def test_throughput_lattice_4096_against_oracle(model):
-    """4096^2 spinodal workload (van der Waals, Tr = 0.7, mean density with a
-    seeded +-1 % perturbation) in the benchmark's launch configuration:
-    three FP64 steps compared with the oracle on every node, and the
-    FP32-shifted path within its bound."""
-    a, b, R, T = 9 / 49, 2 / 21, 1.0, 0.7 * 4 / 7
-    rl, rv, _ = th.maxwell(th.VDW, a, b, R, T)
+@pytest.mark.parametrize("eos", ["vdw", "cs"])
+def test_throughput_lattice_4096_against_oracle(model, eos):
+    """4096^2 spinodal workloads (mean density with a seeded +-1 %
+    perturbation): van der Waals at Tr = 0.7 and the benchmark's
+    Carnahan-Starling a = 0.25 at Tr = 0.85, in the benchmark's launch
+    configuration: three FP64 steps compared with the oracle on every node,
+    and the FP32-shifted path within its bound."""
+    if eos == "vdw":
+        E, a, b, R, T = lbm.EOS_VDW, 9 / 49, 2 / 21, 1.0, 0.7 * 4 / 7
+    else:
+        E, a, b, R = lbm.EOS_CS, 0.25, 4.0, 1.0
+        T = cs_T(a, 0.85)
+    rl, rv, _ = th.maxwell(E, a, b, R, T)
     rho0 = inputs.spinodal(4096, 4096, 0.5 * (rl + rv), 0.01, seed=3)
     if model == "P":
-        cfg = lbm.Config(4096, 4096, lbm.MODEL_P, lbm.EOS_VDW, a, b, R, T)
+        cfg = lbm.Config(4096, 4096, lbm.MODEL_P, E, a, b, R, T)
     else:
         tau = [1.0] * 9
         tau[1] = 0.75
-        cfg = lbm.Config(4096, 4096, lbm.MODEL_FE, lbm.EOS_VDW, a, b, R, T, tau=tau, kappa=0.5)
+        cfg = lbm.Config(4096, 4096, lbm.MODEL_FE, E, a, b, R, T, tau=tau, kappa=0.5)
     steps = 3
     obs, rho, _, _ = gpu_run(cfg, rho0, steps, probe=(2048, 2048))
     ref = oracle_run(cfg, rho0, steps)
@@ -334,3 +340,33 @@ def test_throughput_lattice_4096_against_oracle(model):
     cfg.precision = lbm.FP32_SHIFTED
     _, rho32, _, _ = gpu_run(cfg, rho0, steps, probe=(2048, 2048))
     assert rel_err(rho32, rref) < fp32_tol(steps, rref)
+
+
+# ------------------------------------------------------------------ launch variants
+KF = [0,
+      lbm.KF_SET | lbm.KF_NT_STORE,
+      lbm.KF_SET | lbm.KF_NT_STORE | lbm.KF_REGCAP,
+      lbm.KF_SET | lbm.KF_NT_STORE | lbm.KF_PIPELINE,
+      lbm.KF_SET | lbm.KF_REGCAP | lbm.KF_PIPELINE]
+
+
+@pytest.mark.parametrize("model", ["P", "FE"])
+@pytest.mark.parametrize("kf", KF)
+@pytest.mark.parametrize("tile", [(256, 0), (64, 7), (256, 1)])
+@pytest.mark.parametrize("prec", [lbm.FP64, lbm.FP32_SHIFTED])
+def test_every_launch_variant_matches_oracle(model, kf, tile, prec):
+    """Every kernel variant (store kind, register cap, pipelined row loop)
+    and launch shape (strip width, segment height incl. 1 row and the
+    occupancy-derived default) gives the oracle's field on a ragged
+    lattice (FP64 within 1e-10, FP32-shifted within its bound)."""
+    cfg = p_cfg(300, 130, a=0.25, Tr=0.8) if model == "P" else fe_cfg(300, 130, Tr=0.8)
+    rho0 = droplet_rho(cfg, 30.0)
+    steps = 40
+    ref = oracle_run(cfg, rho0, steps)
+    rref, _, _ = ref.fields()
+    cfg = cfg.with_launch(tile[0], tile[1], kf)
+    cfg.precision = prec
+    obs, rho, _, _ = gpu_run(cfg, rho0, steps)
+    tol = FP64_RTOL if prec == lbm.FP64 else fp32_tol(steps, rref)
+    assert rel_err(rho, rref) < tol
+    assert obs["flags"] == ref.flags
