@@ -443,3 +443,38 @@ def test_psi_clamp_flag_on_vdw_flat_interface():
     s = oracle.Simulation(p, rho0)
     s.step(10)
     assert s.flags == oracle.FLAG_PSI_CLAMP
+
+
+# ---- Laplace's law (Sec. 5.2, Fig. 3) ---------------------------------------
+@pytest.mark.parametrize("model", ["FE", "P"])
+def test_laplace_law(model):
+    """Static droplets obey dp = gamma / R with gamma the planar theory's
+    surface tension: App. B Eq. 15 with the Eq. 26 profile (FE), Eq. 46 with
+    kappa^Li matched to the same value (P).  C-S a = 0.25, Tr = 0.7, 96^2
+    box, R = 16 and 24 (R/W >= 3), 8000 steps.  Curvature (Tolman) and
+    O(dx^2) corrections are ~0.5 % here; the bar is 2 % on dp R_e and 3 % on
+    the two-radius slope."""
+    a, L = 0.25, 96
+    T = 0.7 * th.critical(th.CS, a, 4.0, 1.0)[0]
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    gamma = th.fe_planar(th.CS, a, 4.0, 1.0, T, 0.5)["gamma"]
+    tau = [1.0] * 9
+    if model == "FE":
+        tau[1] = 0.75
+        p = oracle.OracleParams(L, L, oracle.MODEL_FE, oracle.EOS_CS, a, 4.0, 1.0, T, tau=tau,
+                                kappa=0.5)
+    else:
+        m = th.match_p_to_fe(th.CS, a, 4.0, 1.0, T, 0.5)
+        tau[4] = tau[6] = 1 / 1.99
+        p = oracle.OracleParams(L, L, oracle.MODEL_P, oracle.EOS_CS, a, 4.0, 1.0, T, tau=tau,
+                                sigma_li=m["sigma_li"], kappa_p=m["kappa_p"], kappa_li=m["kappa_li"])
+    pts = []
+    for R in (16.0, 24.0):
+        s = oracle.Simulation(p, inputs.droplet(L, L, rl, rv, radius=R))
+        s.step(8000)
+        o = s.observe(L // 2, L // 2)
+        assert o["flags"] == 0
+        assert abs(o["dp"] * o["r_equimolar"] / gamma - 1) < 0.02
+        pts.append((1.0 / o["r_equimolar"], o["dp"]))
+    slope = (pts[1][1] - pts[0][1]) / (pts[1][0] - pts[0][0])
+    assert abs(slope / gamma - 1) < 0.03
