@@ -19,6 +19,9 @@ SOURCES = [os.path.join(_HERE, "csrc", "lbm_kernels.hip"),
            os.path.join(_HERE, "csrc", "mlp_kernels.hip"),
            os.path.join(_HERE, "csrc", "thermo.cpp")]
 OUT = os.path.join(_HERE, "liblbm.so")
+DEMO_SRC = os.path.join(_HERE, "csrc", "lbm_cdemo.c")
+DEMO = os.path.join(_HERE, "lbm_cdemo")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
 def hipcc() -> str:
@@ -39,7 +42,25 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed")
     os.replace(OUT + ".tmp", OUT)
+    build_demo(verbose)
     return OUT
+
+
+def build_demo(verbose: bool = False) -> str:
+    """The plain C client of the C ABI (csrc/lbm_cdemo.c), linked against
+    liblbm.so next to it and the HIP runtime."""
+    cmd = [shutil.which("gcc") or "gcc", "-O2", "-std=c11", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROCM, "include"), "-I", os.path.join(_ROOT, "include"), DEMO_SRC,
+           "-L", _HERE, "-llbm", "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", DEMO + ".tmp"]
+    if verbose:
+        print(" ".join(cmd))
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("gcc failed on the C ABI client")
+    os.replace(DEMO + ".tmp", DEMO)
+    return DEMO
 
 
 if __name__ == "__main__":

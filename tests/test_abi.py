@@ -156,3 +156,13 @@ def test_fe_theory_and_matching(a, Tr, kappa):
     assert math.isclose(sig, m["sigma_li"], rel_tol=1e-10)
     assert math.isclose(kp, m["kappa_p"], rel_tol=1e-8)
     assert math.isclose(kli, m["kappa_li"], rel_tol=1e-7, abs_tol=1e-8)
+
+
+def test_c_client_is_built_against_the_library():
+    """build() also links the plain C client of the ABI (no GPU needed to
+    check that it exists and resolves liblbm.so next to it)."""
+    import subprocess
+    from paper_2403_11167_amd import build as pkg_build
+    assert os.path.exists(pkg_build.DEMO)
+    out = subprocess.run(["ldd", pkg_build.DEMO], capture_output=True, text=True).stdout
+    assert "liblbm.so" in out and "not found" not in out.split("liblbm.so", 1)[1].splitlines()[0]
