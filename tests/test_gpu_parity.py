@@ -147,6 +147,29 @@ def test_droplet_256(model, Tr, R):
     assert obs["flags"] == 0 == ref.flags
 
 
+@pytest.mark.parametrize("model,Tr,R", [("FE", 0.8, 30), ("P", 0.7, 40)])
+def test_droplet_256_full_length(model, Tr, R):
+    """The droplet configuration at its stated length: 256^2, 50000 steps,
+    FP64 against the oracle (field-relative 1e-10, converged run, see
+    field_rel_err), and FP32-shifted storage on the same run within 1e-4 on
+    the bulk densities inside and outside the droplet."""
+    cfg = p_cfg(256, 256, a=1.0, Tr=Tr) if model == "P" else fe_cfg(256, 256, a=0.25, Tr=Tr)
+    rho0 = droplet_rho(cfg, R)
+    steps = 50000
+    ref = oracle_run(cfg, rho0, steps)
+    rref, _, _ = ref.fields()
+    obs, rho, _, _ = gpu_run(cfg, rho0, steps, probe=(128, 128))
+    assert field_rel_err(rho, rref) < FP64_RTOL
+    assert obs["flags"] == ref.flags == 0
+    o = ref.observe(128, 128)
+    assert math.isclose(obs["rho_in"], o["rho_in"], rel_tol=1e-9)
+    assert math.isclose(obs["rho_out"], o["rho_out"], rel_tol=1e-9)
+    cfg.precision = lbm.FP32_SHIFTED
+    obs32, rho32, _, _ = gpu_run(cfg, rho0, steps, probe=(128, 128))
+    assert abs(obs32["rho_in"] / o["rho_in"] - 1) < FP32_COEX_RTOL
+    assert abs(obs32["rho_out"] / o["rho_out"] - 1) < FP32_COEX_RTOL
+
+
 SHAPES = [(1, 1), (2, 3), (5, 7), (257, 9), (300, 130), (513, 70), (64, 257)]
 
 
