@@ -48,13 +48,15 @@ class _Params(ctypes.Structure):
                 ("tau", ctypes.c_double * 9),
                 ("sigma_li", ctypes.c_double), ("kappa_li", ctypes.c_double),
                 ("kappa_p", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("fx", ctypes.c_double), ("fy", ctypes.c_double)]
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("walls", ctypes.c_int32)]
 
 
 @dataclass
 class OracleParams:
     """Problem statement of Sec. 2 / Sec. 5: periodic grid, model, EOS,
-    MRT relaxation times (Eq. 3), model coefficients, body force."""
+    MRT relaxation times (Eq. 3), model coefficients, body force; walls = 1
+    puts Zou-He no-slip walls on the rows y = 0 and y = ny - 1 (Sec. 5.3)."""
     nx: int
     ny: int
     model: int
@@ -70,6 +72,7 @@ class OracleParams:
     kappa: float = 0.0
     fx: float = 0.0
     fy: float = 0.0
+    walls: int = 0
 
     def _c(self) -> _Params:
         p = _Params()
@@ -79,6 +82,7 @@ class OracleParams:
             p.tau[i] = t
         p.sigma_li, p.kappa_li, p.kappa_p = self.sigma_li, self.kappa_li, self.kappa_p
         p.kappa, p.fx, p.fy = self.kappa, self.fx, self.fy
+        p.walls = int(self.walls)
         return p
 
 

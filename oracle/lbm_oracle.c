@@ -44,6 +44,13 @@
  *       with F_b a constant body force (zero in all standard workloads);
  *       the consistency term uses F_int only.  For the free-energy model the
  *       total force is -rho grad(mu) + F_b.
+ *   R7  Walls (Sec. 5.3, optional): no-slip walls of Zou and He on the rows
+ *       y = 0 and y = ny - 1, which are fluid nodes whose velocity is held at
+ *       zero; x stays periodic.  The paper does not say how the stencils see
+ *       past a wall: values on the rows beyond it mirror the rows inside
+ *       (rho, psi, mu at y = -k equal those at y = k), so the density has no
+ *       normal gradient at the wall and the normal interaction force there
+ *       vanishes.
  */
 #include <math.h>
 #include <stdint.h>
@@ -71,6 +78,7 @@ typedef struct {
   double sigma_li, kappa_li, kappa_p; /* pseudopotential only */
   double kappa;                       /* free energy only */
   double fx, fy;                      /* constant body force */
+  int32_t walls; /* 0: periodic in y; 1: Zou-He walls on y = 0, ny-1 (R7) */
 } orc_params;
 
 /* ---- lattice (Eq. 2 and the weights stated under Eq. 4) ------------------ */
@@ -224,17 +232,27 @@ static int wrap(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
+/* Row whose values a stencil sees at row y: periodic, or with walls (R7)
+ * the mirror image of the rows inside. */
+static int row_seen(int y, int ny, int walls) {
+  if (!walls) return wrap(y, ny);
+  if (y < 0) return -y;
+  if (y > ny - 1) return 2 * (ny - 1) - y;
+  return y;
+}
+
 /* ---- stencils on a periodic field (exposed for unit tests) --------------- */
 
 /* Shan-Chen neighbour sum S_a = sum_{i=1..8} omega_i phi(x+c_i) c_ia, so that
  * Eq. 10 reads F_a = -G psi(x) S_a. */
-void orc_sc_sum(int nx, int ny, const double *phi, double *Sx, double *Sy) {
+static void sc_sum(int nx, int ny, int walls, const double *phi, double *Sx,
+                   double *Sy) {
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       double sx = 0.0, sy = 0.0;
       for (int i = 1; i < 9; ++i) {
-        double v = phi[wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)];
+        double v = phi[row_seen(y + CY[i], ny, walls) * nx + wrap(x + CX[i], nx)];
         sx += omega_sc(i) * v * CX[i];
         sy += omega_sc(i) * v * CY[i];
       }
@@ -243,9 +261,14 @@ void orc_sc_sum(int nx, int ny, const double *phi, double *Sx, double *Sy) {
     }
 }
 
+void orc_sc_sum(int nx, int ny, const double *phi, double *Sx, double *Sy) {
+  sc_sum(nx, ny, 0, phi, Sx, Sy);
+}
+
 /* Eq. 30a-b with C_1 of Eq. 31a and C_2 read as (G/2)(1 - kappa^P) (R1). */
-void orc_q_tensor(int nx, int ny, const double *psi, double kappa_p,
-                  double kappa_li, double *Qxx, double *Qyy, double *Qxy) {
+static void q_tensor(int nx, int ny, int walls, const double *psi,
+                     double kappa_p, double kappa_li, double *Qxx, double *Qyy,
+                     double *Qxy) {
   double C1 = 5.0 / 6.0 * (kappa_p - 1.0);
   double C2 = 0.5 * G * (1.0 - kappa_p);
 #pragma omp parallel for schedule(static)
@@ -254,7 +277,7 @@ void orc_q_tensor(int nx, int ny, const double *psi, double kappa_p,
       double p0 = psi[y * nx + x];
       double q[2][2] = {{0, 0}, {0, 0}};
       for (int i = 1; i < 9; ++i) {
-        double d = psi[wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)] - p0;
+        double d = psi[row_seen(y + CY[i], ny, walls) * nx + wrap(x + CX[i], nx)] - p0;
         int c[2] = {CX[i], CY[i]};
         for (int al = 0; al < 2; ++al)
           for (int be = 0; be < 2; ++be) {
@@ -270,14 +293,20 @@ void orc_q_tensor(int nx, int ny, const double *psi, double kappa_p,
     }
 }
 
+void orc_q_tensor(int nx, int ny, const double *psi, double kappa_p,
+                  double kappa_li, double *Qxx, double *Qyy, double *Qxy) {
+  q_tensor(nx, ny, 0, psi, kappa_p, kappa_li, Qxx, Qyy, Qxy);
+}
+
 /* Eq. 24, first line, with the weights w_i (R2). */
-void orc_gradient(int nx, int ny, const double *phi, double *gx, double *gy) {
+static void gradient(int nx, int ny, int walls, const double *phi, double *gx,
+                     double *gy) {
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       double sx = 0.0, sy = 0.0;
       for (int i = 0; i < 9; ++i) {
-        double v = phi[wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)];
+        double v = phi[row_seen(y + CY[i], ny, walls) * nx + wrap(x + CX[i], nx)];
         sx += WGT[i] * v * CX[i];
         sy += WGT[i] * v * CY[i];
       }
@@ -286,16 +315,24 @@ void orc_gradient(int nx, int ny, const double *phi, double *gx, double *gy) {
     }
 }
 
+void orc_gradient(int nx, int ny, const double *phi, double *gx, double *gy) {
+  gradient(nx, ny, 0, phi, gx, gy);
+}
+
 /* Eq. 24, second line. */
-void orc_laplacian(int nx, int ny, const double *phi, double *lap) {
+static void laplacian(int nx, int ny, int walls, const double *phi, double *lap) {
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       double c = phi[y * nx + x], s = 0.0;
       for (int i = 0; i < 9; ++i)
-        s += WGT[i] * (phi[wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx)] - c);
+        s += WGT[i] * (phi[row_seen(y + CY[i], ny, walls) * nx + wrap(x + CX[i], nx)] - c);
       lap[y * nx + x] = 2.0 * s / CS2;
     }
+}
+
+void orc_laplacian(int nx, int ny, const double *phi, double *lap) {
+  laplacian(nx, ny, 0, phi, lap);
 }
 
 /* ---- exported small helpers ---------------------------------------------- */
@@ -336,6 +373,43 @@ void orc_init(const orc_params *p, const double *rho0, const double *ux0,
   }
 }
 
+/* ---- Zou-He no-slip walls (R7) --------------------------------------------
+ * Row y is a wall row if walls are on and y is 0 or ny - 1; side +1 is the
+ * bottom wall (the populations with c_y = +1 are unknown after streaming,
+ * they would come from below it), side -1 the top wall. */
+static int wall_side(const orc_params *p, int y) {
+  if (!p->walls) return 0;
+  if (y == 0) return 1;
+  if (y == p->ny - 1) return -1;
+  return 0;
+}
+
+/* Replace the unknown populations fn[i] (c_y = side) of a wall node so that
+ * the node carries the momentum sum_i f_i c_i = (jx, jy).  Zou and He's
+ * closure: the normal unknown takes the value of its opposite (the
+ * non-equilibrium parts bounce back; at the wall velocity u_w = 0 the two
+ * equilibria are equal), then the two diagonal unknowns solve the x and y
+ * momentum balances.  For u = u_w = 0 under Eq. 6b, (jx, jy) = -F/2. */
+static void wall_close(double *fn, int side, double jx, double jy) {
+  int nrm = -1, opp = -1, d[2], nd = 0;
+  for (int i = 1; i < 9; ++i) {
+    if (CY[i] == side && CX[i] == 0) nrm = i;
+    if (CY[i] == -side && CX[i] == 0) opp = i;
+    if (CY[i] == side && CX[i] != 0) d[nd++] = i;
+  }
+  fn[nrm] = fn[opp];
+  double bx = jx, by = jy;
+  for (int i = 0; i < 9; ++i)
+    if (i != d[0] && i != d[1]) {
+      bx -= fn[i] * CX[i];
+      by -= fn[i] * CY[i];
+    }
+  /* [CX[d0] CX[d1]; CY[d0] CY[d1]] (f_d0, f_d1) = (bx, by), Cramer's rule */
+  double det = (double)(CX[d[0]] * CY[d[1]] - CX[d[1]] * CY[d[0]]);
+  fn[d[0]] = (bx * CY[d[1]] - CX[d[1]] * by) / det;
+  fn[d[1]] = (CX[d[0]] * by - CY[d[0]] * bx) / det;
+}
+
 /* Per-step field work shared by the step and by the field export: density,
  * and the model's force ingredients.  Arrays are length N. */
 typedef struct {
@@ -365,8 +439,13 @@ static unsigned fields_and_forces(const orc_params *p, const double *f,
   unsigned flags = 0;
 #pragma omp parallel for schedule(static) reduction(| : flags)
   for (size_t n = 0; n < N; ++n) {
-    double s = 0.0;
-    for (int i = 0; i < 9; ++i) s += f[i * N + n];
+    double fn[9], s = 0.0;
+    for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
+    int side = wall_side(p, (int)(n / (size_t)nx));
+    /* the density of a wall node does not depend on jx; jy = -F_y/2 with
+     * F_y = fy there, the normal interaction force vanishing (R7) */
+    if (side) wall_close(fn, side, 0.0, -0.5 * p->fy);
+    for (int i = 0; i < 9; ++i) s += fn[i];
     w->rho[n] = s;
     if (!isfinite(s)) flags |= ORC_FLAG_NONFINITE;
     if (!eos_domain_ok(p, s)) flags |= ORC_FLAG_EOS_DOMAIN;
@@ -374,16 +453,16 @@ static unsigned fields_and_forces(const orc_params *p, const double *f,
   if (p->model == ORC_MODEL_P) {
 #pragma omp parallel for schedule(static) reduction(| : flags)
     for (size_t n = 0; n < N; ++n) w->psi[n] = psi_of_rho(p, w->rho[n], &flags);
-    orc_sc_sum(nx, ny, w->psi, w->Sx, w->Sy);
-    orc_q_tensor(nx, ny, w->psi, p->kappa_p, p->kappa_li, w->Qxx, w->Qyy, w->Qxy);
+    sc_sum(nx, ny, p->walls, w->psi, w->Sx, w->Sy);
+    q_tensor(nx, ny, p->walls, w->psi, p->kappa_p, p->kappa_li, w->Qxx, w->Qyy, w->Qxy);
   } else {
     /* mu = mu_b(rho) - kappa lap(rho) (Sec. 2.2), then grad(mu), grad(rho). */
-    orc_laplacian(nx, ny, w->rho, w->lap);
+    laplacian(nx, ny, p->walls, w->rho, w->lap);
 #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; ++n)
       w->mu[n] = eos_mu_b(p, w->rho[n]) - p->kappa * w->lap[n];
-    orc_gradient(nx, ny, w->mu, w->gmx, w->gmy);
-    orc_gradient(nx, ny, w->rho, w->grx, w->gry);
+    gradient(nx, ny, p->walls, w->mu, w->gmx, w->gmy);
+    gradient(nx, ny, p->walls, w->rho, w->grx, w->gry);
   }
   return flags;
 }
@@ -413,11 +492,14 @@ uint32_t orc_fields(const orc_params *p, const double *f, double *rho,
   work_alloc(&w, N);
   unsigned flags = fields_and_forces(p, f, &w);
   for (size_t n = 0; n < N; ++n) {
-    double Fx, Fy, K, jx = 0.0, jy = 0.0;
+    double Fx, Fy, K, jx = 0.0, jy = 0.0, fn[9];
     node_force(p, &w, n, &Fx, &Fy, &K);
+    for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
+    int side = wall_side(p, (int)(n / (size_t)p->nx));
+    if (side) wall_close(fn, side, -0.5 * Fx, -0.5 * p->fy);
     for (int i = 0; i < 9; ++i) {
-      jx += f[i * N + n] * CX[i];
-      jy += f[i * N + n] * CY[i];
+      jx += fn[i] * CX[i];
+      jy += fn[i] * CY[i];
     }
     if (rho) rho[n] = w.rho[n];
     if (ux) ux[n] = (jx + 0.5 * Fx) / w.rho[n];
@@ -436,6 +518,8 @@ static void collide_node(const orc_params *p, const double *f, size_t N,
   double rho = w->rho[n];
   for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
   node_force(p, w, n, &Fx, &Fy, &K);
+  int side = wall_side(p, (int)(n / (size_t)p->nx));
+  if (side) wall_close(fn, side, -0.5 * Fx, -0.5 * p->fy);
 
   /* Eq. 6b. */
   double jx = 0.0, jy = 0.0;
@@ -486,7 +570,9 @@ static void collide_node(const orc_params *p, const double *f, size_t N,
 }
 
 /* Advance nsteps time steps in place.  Returns the OR of the sticky flags
- * raised on the way.  Streaming: f_i(x + c_i, t + 1) = f*_i(x, t), periodic. */
+ * raised on the way.  Streaming: f_i(x + c_i, t + 1) = f*_i(x, t), periodic.
+ * With walls, what streams across a wall lands in the unknown slots of the
+ * opposite wall row, which the closure overwrites before any use. */
 uint32_t orc_step(const orc_params *p, double *f, int64_t nsteps) {
   int nx = p->nx, ny = p->ny;
   size_t N = (size_t)nx * ny;

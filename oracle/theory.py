@@ -390,3 +390,43 @@ def discrete_planar_p(eos, a, b, R, T, kappa_p, sigma_li, rho_init):
     if not ok:
         raise RuntimeError("discrete P planar solve did not converge")
     return x[:N], x[N]
+
+
+# --------------------------------------------------------------------------
+# two-phase flow between parallel plates (Sec. 5.3, App. F)
+def plates_sharp(Fx, H, mu1, mu2, y):
+    """App. F Eq. 88: steady velocity between no-slip plates at y = 0 and
+    y = H, fluid 1 (dynamic viscosity mu1) below H/2 and fluid 2 (mu2) above,
+    driven by the body force Fx, with velocity and shear stress continuous at
+    the sharp interface y = H/2.  C_1 as printed; C_2 is the value that
+    u_1(0) = 0 requires, F_x H^2 / (8 mu1) - C_1 H / 2 (the printed C_2 has
+    H for H^2 and the opposite sign of its first term, which violates the
+    no-slip condition it is meant to satisfy)."""
+    y = np.asarray(y, dtype=np.float64)
+    C1 = Fx * H / 4 * (mu2 - mu1) / (mu1 * (mu1 + mu2))
+    C2 = Fx * H * H / (8 * mu1) - C1 * H / 2
+    u1 = -Fx / (2 * mu1) * (H / 2 - y) ** 2 + C1 * (H / 2 - y) + C2
+    u2 = -Fx / (2 * mu2) * (y - H / 2) ** 2 - mu1 * C1 / mu2 * (y - H / 2) + C2
+    return np.where(y <= H / 2, u1, u2)
+
+
+def plates_diffuse(Fx, y_nodes, mu_nodes, refine=64):
+    """App. F Eq. 89: steady velocity between no-slip plates at y_nodes[0]
+    and y_nodes[-1] for a viscosity mu(y) that varies continuously,
+    u(y) = -Fx int_0^y y'/mu dy' + mu(0) u'(0) int_0^y dy'/mu, with the
+    constant mu(0) u'(0) fixed by u = 0 on the upper plate.  mu(y) is the
+    cubic spline through the nodal values (mu = rho c_s^2 (tau_nu - 1/2) of a
+    density profile); the integrals use composite Simpson on a grid refined
+    refine times.  Returns u at y_nodes."""
+    from scipy.interpolate import CubicSpline
+    y_nodes = np.asarray(y_nodes, dtype=np.float64)
+    y0 = y_nodes[0]
+    spl = CubicSpline(y_nodes - y0, np.asarray(mu_nodes, dtype=np.float64))
+    n = (len(y_nodes) - 1) * refine + 1
+    yf = np.linspace(0.0, y_nodes[-1] - y0, n)
+    mu = spl(yf)
+    i1 = _cumulative(yf / mu, yf)
+    i0 = _cumulative(1.0 / mu, yf)
+    c = Fx * i1[-1] / i0[-1]
+    u = -Fx * i1 + c * i0
+    return u[::refine]

@@ -38,6 +38,19 @@ def planar_slab(nx: int, ny: int, rho_l: float, rho_v: float, width: float = 5.0
     return rho
 
 
+def layered(nx: int, ny: int, rho_l: float, rho_v: float, width: float = 5.0,
+            y_i: float | None = None) -> np.ndarray:
+    """rho(y) = (rho_l + rho_v)/2 + (rho_l - rho_v)/2 tanh(2 (y - y_i)/W):
+    vapour below, liquid above one interface parallel to the x axis (the
+    channel between two walls, Sec. 5.3).  Default y_i = (ny - 1)/2, the
+    mid-plane between wall rows 0 and ny - 1."""
+    if y_i is None:
+        y_i = 0.5 * (ny - 1)
+    y = np.arange(ny, dtype=np.float64)
+    prof = 0.5 * (rho_l + rho_v) + 0.5 * (rho_l - rho_v) * np.tanh(2 * (y - y_i) / width)
+    return np.broadcast_to(prof[:, None], (ny, nx)).copy()
+
+
 def droplet(nx: int, ny: int, rho_l: float, rho_v: float, radius: float,
             width: float = 5.0, cx: float | None = None, cy: float | None = None) -> np.ndarray:
     """rho = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh(2 (r - R)/W), centred
