@@ -49,14 +49,21 @@ class _Params(ctypes.Structure):
                 ("sigma_li", ctypes.c_double), ("kappa_li", ctypes.c_double),
                 ("kappa_p", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("fx", ctypes.c_double), ("fy", ctypes.c_double),
-                ("walls", ctypes.c_int32)]
+                ("walls", ctypes.c_int32), ("x_split", ctypes.c_int32),
+                ("ax", ctypes.c_double), ("rho_ave", ctypes.c_double),
+                ("A", ctypes.c_double)]
 
 
 @dataclass
 class OracleParams:
     """Problem statement of Sec. 2 / Sec. 5: periodic grid, model, EOS,
     MRT relaxation times (Eq. 3), model coefficients, body force; walls = 1
-    puts Zou-He no-slip walls on the rows y = 0 and y = ny - 1 (Sec. 5.3)."""
+    puts Zou-He no-slip walls on the rows y = 0 and y = ny - 1 (Sec. 5.3).
+    ax != 0 adds the droplet-collision drive of Sec. 5.4, an x force
+    a(x) |rho - rho_ave| with a = +ax for x <= x_split and -ax beyond, in the
+    steps that start at t >= ax_from_step; rho_ave <= 0 takes the mean of
+    the initial density.  Free energy only: A is the viscosity-tuning
+    parameter of Eq. 20."""
     nx: int
     ny: int
     model: int
@@ -73,6 +80,11 @@ class OracleParams:
     fx: float = 0.0
     fy: float = 0.0
     walls: int = 0
+    ax: float = 0.0
+    x_split: int = 0
+    rho_ave: float = 0.0
+    ax_from_step: int = 0
+    A: float = 0.0
 
     def _c(self) -> _Params:
         p = _Params()
@@ -83,6 +95,8 @@ class OracleParams:
         p.sigma_li, p.kappa_li, p.kappa_p = self.sigma_li, self.kappa_li, self.kappa_p
         p.kappa, p.fx, p.fy = self.kappa, self.fx, self.fy
         p.walls = int(self.walls)
+        p.x_split, p.ax, p.rho_ave = int(self.x_split), float(self.ax), float(self.rho_ave)
+        p.A = float(self.A)
         return p
 
 
@@ -108,6 +122,8 @@ def lib():
         L.orc_feq.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, _D]
         L.orc_forcing_fe.argtypes = [ctypes.c_double] * 6 + [_D]
+        L.orc_feq_fe_full.argtypes = [ctypes.c_double] * 5 + [_D, _D]
+        L.orc_forcing_fe_full.argtypes = [ctypes.c_double] * 7 + [_D]
         L.orc_sc_sum.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D]
         L.orc_q_tensor.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_double,
                                    ctypes.c_double, _D, _D, _D]
@@ -152,6 +168,21 @@ def feq(model: int, rho: float, ux: float, uy: float) -> np.ndarray:
 def forcing_fe(ux, uy, Fx, Fy, gx, gy) -> np.ndarray:
     out = np.zeros(9)
     lib().orc_forcing_fe(ux, uy, Fx, Fy, gx, gy, _ptr(out))
+    return out
+
+
+def feq_fe_full(rho, ux, uy, pg, A, du) -> np.ndarray:
+    """Eq. 20 in full; du = (d_x u_x, d_y u_x, d_x u_y, d_y u_y)."""
+    out = np.zeros(9)
+    lib().orc_feq_fe_full(rho, ux, uy, pg, A, _ptr(np.ascontiguousarray(du, dtype=np.float64)),
+                          _ptr(out))
+    return out
+
+
+def forcing_fe_full(ux, uy, Fx, Fy, gx, gy, dpgy) -> np.ndarray:
+    """Eq. 21 in full, with d_y p_g = dpgy."""
+    out = np.zeros(9)
+    lib().orc_forcing_fe_full(ux, uy, Fx, Fy, gx, gy, dpgy, _ptr(out))
     return out
 
 
@@ -208,10 +239,15 @@ class Simulation:
 
     def __init__(self, params: OracleParams, rho0: np.ndarray,
                  ux0: np.ndarray | None = None, uy0: np.ndarray | None = None):
-        self.p = params
-        self._cp = params._c()
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
         assert rho0.shape == (params.ny, params.nx)
+        if params.ax != 0.0 and params.rho_ave <= 0.0:
+            import dataclasses
+            params = dataclasses.replace(params, rho_ave=math.fsum(rho0.ravel().tolist()) / rho0.size)
+        self.p = params
+        self._cp = params._c()  # the drive on
+        self._cp_off = params._c()
+        self._cp_off.ax = 0.0
         self.f = np.zeros((9, params.ny, params.nx))
         ux0 = None if ux0 is None else np.ascontiguousarray(ux0, dtype=np.float64)
         uy0 = None if uy0 is None else np.ascontiguousarray(uy0, dtype=np.float64)
@@ -220,17 +256,26 @@ class Simulation:
         self.flags = 0
         self.t = 0
 
+    def _cparams(self):
+        return self._cp if self.t >= self.p.ax_from_step else self._cp_off
+
     def step(self, n: int) -> int:
-        fl = lib().orc_step(ctypes.byref(self._cp), _ptr(self.f), int(n))
-        self.flags |= int(fl)
-        self.t += int(n)
+        n = int(n)
+        while n > 0:
+            k = n
+            if self.t < self.p.ax_from_step:
+                k = min(n, self.p.ax_from_step - self.t)
+            fl = lib().orc_step(ctypes.byref(self._cparams()), _ptr(self.f), k)
+            self.flags |= int(fl)
+            self.t += k
+            n -= k
         return self.flags
 
     def fields(self):
         """(rho, ux, uy) of Eq. 6a-b for the current populations."""
         shp = (self.p.ny, self.p.nx)
         rho, ux, uy = np.zeros(shp), np.zeros(shp), np.zeros(shp)
-        fl = lib().orc_fields(ctypes.byref(self._cp), _ptr(self.f), _ptr(rho),
+        fl = lib().orc_fields(ctypes.byref(self._cparams()), _ptr(self.f), _ptr(rho),
                               _ptr(ux), _ptr(uy))
         self.flags |= int(fl)
         return rho, ux, uy

@@ -51,6 +51,18 @@
  *       (rho, psi, mu at y = -k equal those at y = k), so the density has no
  *       normal gradient at the wall and the normal interaction force there
  *       vanishes.
+ *   R8  The droplet-collision drive (Sec. 5.4, optional): an x force
+ *       a(x) |rho - rho_ave| with a(x) = +ax for x <= x_split and -ax beyond,
+ *       added to the body force; rho_ave, the mean density, is a constant
+ *       because the scheme conserves mass (Eq. 7a).  It joins F_b of R6.
+ *   R9  Free energy with A != 0 (Eq. 20, optional): S_ab = d_a u_b +
+ *       d_b u_a with the gradient stencil of Eq. 24 applied to the velocity
+ *       field of the same time step (Eq. 6b at every node first); past a
+ *       wall the velocity is reflected with its sign flipped, so it vanishes
+ *       on the wall row as the closure imposes.  The initial equilibrium
+ *       takes S from the initial velocity the same way (zero for a fluid at
+ *       rest).  Gravity (p_g, F_g) is written into the equilibrium and
+ *       forcing functions but not used by the step.
  */
 #include <math.h>
 #include <stdint.h>
@@ -79,6 +91,9 @@ typedef struct {
   double kappa;                       /* free energy only */
   double fx, fy;                      /* constant body force */
   int32_t walls; /* 0: periodic in y; 1: Zou-He walls on y = 0, ny-1 (R7) */
+  int32_t x_split;      /* drive (R8): +ax for x <= x_split, -ax beyond */
+  double ax, rho_ave;   /* drive (R8); ax = 0: off */
+  double A;             /* free energy: viscosity-tuning A of Eq. 20 (R9) */
 } orc_params;
 
 /* ---- lattice (Eq. 2 and the weights stated under Eq. 4) ------------------ */
@@ -197,23 +212,37 @@ static void feq_standard(double rho, double ux, double uy, double *feq) {
   }
 }
 
-/* Eq. 20 with p_g = 0 and A = 0 (free energy); c_s^4 in the i != 0 term as
- * printed in Eq. 20. */
-static void feq_well_balanced(double rho, double ux, double uy, double *feq) {
+/* Eq. 20 (free energy); c_s^4 in the i != 0 term as printed in Eq. 20.
+ * pg is p_g at the node, A the viscosity-tuning parameter and du[] the
+ * velocity gradient (d_x u_x, d_y u_x, d_x u_y, d_y u_y), giving
+ * S_ab = d_a u_b + d_b u_a (NULL: zero). */
+static void feq_well_balanced(double rho, double ux, double uy, double pg,
+                              double A, const double *du, double *feq) {
   double uu = ux * ux + uy * uy;
-  feq[0] = rho - WGT36[0] * rho * uu / (2.0 * CS2) / 36.0;
+  double Sxx = 0.0, Syy = 0.0, Sxy = 0.0;
+  if (du) {
+    Sxx = 2.0 * du[0];
+    Syy = 2.0 * du[3];
+    Sxy = du[1] + du[2];
+  }
+  double divu = 0.5 * (Sxx + Syy);
+  feq[0] = rho - (36.0 - WGT36[0]) * pg / CS2 / 36.0 -
+           WGT36[0] * rho * uu / (2.0 * CS2) / 36.0 - WGT36[0] * rho * A * divu / 36.0;
   for (int i = 1; i < 9; ++i) {
     double cu = CX[i] * ux + CY[i] * uy;
-    double quad = (cu * cu - CS2 * uu) / (2.0 * CS2 * CS2);
-    feq[i] = WGT36[i] * rho * (cu / CS2 + quad) / 36.0;
+    /* (c_a c_b - c_s^2 delta_ab)(u_a u_b + c_s^2 A S_ab) */
+    double cSc = CX[i] * CX[i] * Sxx + 2.0 * CX[i] * CY[i] * Sxy + CY[i] * CY[i] * Syy;
+    double tensor = (cu * cu - CS2 * uu) + CS2 * A * (cSc - CS2 * (Sxx + Syy));
+    double quad = tensor / (2.0 * CS2 * CS2);
+    feq[i] = WGT36[i] * (pg / CS2 + rho * (cu / CS2 + quad)) / 36.0;
   }
 }
 
-/* Eq. 21 with p_g = 0, d = 2: velocity-space forcing of the free-energy
- * model, with gx, gy the stencil gradient of rho. */
+/* Eq. 21 with d = 2: velocity-space forcing of the free-energy model, with
+ * gx, gy the stencil gradient of rho and dpgy = d_y p_g. */
 static void forcing_well_balanced(double ux, double uy, double Fx, double Fy,
-                                  double gx, double gy, double *Fi) {
-  double Bx = Fx + CS2 * gx, By = Fy + CS2 * gy;
+                                  double gx, double gy, double dpgy, double *Fi) {
+  double Bx = Fx + CS2 * gx, By = Fy - dpgy + CS2 * gy;
   double ug = ux * gx + uy * gy;
   for (int i = 0; i < 9; ++i) {
     double cF = CX[i] * Fx + CY[i] * Fy;
@@ -335,6 +364,26 @@ void orc_laplacian(int nx, int ny, const double *phi, double *lap) {
   laplacian(nx, ny, 0, phi, lap);
 }
 
+/* Eq. 24 gradient of a velocity component (R9): past a wall the value of
+ * the mirrored row enters with its sign flipped. */
+static void gradient_u(int nx, int ny, int walls, const double *u, double *gx,
+                       double *gy) {
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double sx = 0.0, sy = 0.0;
+      for (int i = 0; i < 9; ++i) {
+        int yy = y + CY[i];
+        double sgn = (walls && (yy < 0 || yy > ny - 1)) ? -1.0 : 1.0;
+        double v = sgn * u[row_seen(yy, ny, walls) * nx + wrap(x + CX[i], nx)];
+        sx += WGT[i] * v * CX[i];
+        sy += WGT[i] * v * CY[i];
+      }
+      gx[y * nx + x] = sx / CS2;
+      gy[y * nx + x] = sy / CS2;
+    }
+}
+
 /* ---- exported small helpers ---------------------------------------------- */
 double orc_pressure(const orc_params *p, double rho) { return eos_pressure(p, rho); }
 double orc_mu_b(const orc_params *p, double rho) { return eos_mu_b(p, rho); }
@@ -349,13 +398,22 @@ void orc_matrices(double *m, double *minv, double *minv36) {
 }
 void orc_feq(int32_t model, double rho, double ux, double uy, double *feq) {
   if (model == ORC_MODEL_FE)
-    feq_well_balanced(rho, ux, uy, feq);
+    feq_well_balanced(rho, ux, uy, 0.0, 0.0, NULL, feq);
   else
     feq_standard(rho, ux, uy, feq);
 }
+/* Eq. 20 in full: p_g, A and du = (d_x u_x, d_y u_x, d_x u_y, d_y u_y). */
+void orc_feq_fe_full(double rho, double ux, double uy, double pg, double A,
+                     const double *du, double *feq) {
+  feq_well_balanced(rho, ux, uy, pg, A, du, feq);
+}
 void orc_forcing_fe(double ux, double uy, double Fx, double Fy, double gx,
                     double gy, double *Fi) {
-  forcing_well_balanced(ux, uy, Fx, Fy, gx, gy, Fi);
+  forcing_well_balanced(ux, uy, Fx, Fy, gx, gy, 0.0, Fi);
+}
+void orc_forcing_fe_full(double ux, double uy, double Fx, double Fy, double gx,
+                         double gy, double dpgy, double *Fi) {
+  forcing_well_balanced(ux, uy, Fx, Fy, gx, gy, dpgy, Fi);
 }
 
 /* Population layout: f[i * N + y * nx + x], N = nx * ny, holding f_i(x, t)
@@ -365,12 +423,29 @@ void orc_forcing_fe(double ux, double uy, double Fx, double Fy, double gx,
  * equilibrium; u0 may be NULL for a fluid at rest). */
 void orc_init(const orc_params *p, const double *rho0, const double *ux0,
               const double *uy0, double *f) {
-  size_t N = (size_t)p->nx * p->ny;
+  int nx = p->nx, ny = p->ny;
+  size_t N = (size_t)nx * ny;
+  double *du[4] = {NULL, NULL, NULL, NULL};
+  int with_a = p->model == ORC_MODEL_FE && p->A != 0.0 && ux0 && uy0;
+  if (with_a) {
+    for (int k = 0; k < 4; ++k) du[k] = (double *)calloc(N, sizeof(double));
+    gradient_u(nx, ny, p->walls, ux0, du[0], du[1]);
+    gradient_u(nx, ny, p->walls, uy0, du[2], du[3]);
+  }
   for (size_t n = 0; n < N; ++n) {
     double feq[9];
-    orc_feq(p->model, rho0[n], ux0 ? ux0[n] : 0.0, uy0 ? uy0[n] : 0.0, feq);
+    double ux = ux0 ? ux0[n] : 0.0, uy = uy0 ? uy0[n] : 0.0;
+    if (p->model == ORC_MODEL_FE) {
+      double dn[4] = {0.0, 0.0, 0.0, 0.0};
+      if (with_a)
+        for (int k = 0; k < 4; ++k) dn[k] = du[k][n];
+      feq_well_balanced(rho0[n], ux, uy, 0.0, p->A, dn, feq);
+    } else {
+      feq_standard(rho0[n], ux, uy, feq);
+    }
     for (int i = 0; i < 9; ++i) f[i * N + n] = feq[i];
   }
+  for (int k = 0; k < 4; ++k) free(du[k]);
 }
 
 /* ---- Zou-He no-slip walls (R7) --------------------------------------------
@@ -410,17 +485,23 @@ static void wall_close(double *fn, int side, double jx, double jy) {
   fn[d[1]] = (CX[d[0]] * by - CY[d[0]] * bx) / det;
 }
 
+/* Normal momentum sum f c_y = -F_y/2 of a wall node, with F_y = fy its
+ * normal body force: the interaction force vanishes there (R7). */
+static double wall_jy(const orc_params *p) { return -0.5 * p->fy; }
+
 /* Per-step field work shared by the step and by the field export: density,
  * and the model's force ingredients.  Arrays are length N. */
 typedef struct {
   double *rho, *psi, *Sx, *Sy, *Qxx, *Qyy, *Qxy; /* pseudopotential */
   double *lap, *mu, *gmx, *gmy, *grx, *gry;       /* free energy */
+  double *ux, *uy, *du[4];                        /* velocity, its gradient (R9) */
 } orc_work;
 
 static void work_alloc(orc_work *w, size_t N) {
   double **ptrs[] = {&w->rho, &w->psi, &w->Sx,  &w->Sy,  &w->Qxx, &w->Qyy,
                      &w->Qxy, &w->lap, &w->mu,  &w->gmx, &w->gmy, &w->grx,
-                     &w->gry};
+                     &w->gry, &w->ux,  &w->uy,  &w->du[0], &w->du[1],
+                     &w->du[2], &w->du[3]};
   for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k)
     *ptrs[k] = (double *)calloc(N, sizeof(double));
 }
@@ -428,7 +509,8 @@ static void work_alloc(orc_work *w, size_t N) {
 static void work_free(orc_work *w) {
   free(w->rho); free(w->psi); free(w->Sx); free(w->Sy); free(w->Qxx);
   free(w->Qyy); free(w->Qxy); free(w->lap); free(w->mu); free(w->gmx);
-  free(w->gmy); free(w->grx); free(w->gry);
+  free(w->gmy); free(w->grx); free(w->gry); free(w->ux); free(w->uy);
+  for (int k = 0; k < 4; ++k) free(w->du[k]);
 }
 
 /* Eq. 6a, then the model's field quantities (Sec. 2.1 / Sec. 2.2). */
@@ -442,10 +524,11 @@ static unsigned fields_and_forces(const orc_params *p, const double *f,
     double fn[9], s = 0.0;
     for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
     int side = wall_side(p, (int)(n / (size_t)nx));
-    /* the density of a wall node does not depend on jx; jy = -F_y/2 with
-     * F_y = fy there, the normal interaction force vanishing (R7) */
-    if (side) wall_close(fn, side, 0.0, -0.5 * p->fy);
+    if (side) wall_close(fn, side, 0.0, 0.0);
     for (int i = 0; i < 9; ++i) s += fn[i];
+    /* a wall node also carries sum f c_y = jy(rho), which adds jy to its
+     * density (it does not depend on jx) */
+    if (side) s += wall_jy(p);
     w->rho[n] = s;
     if (!isfinite(s)) flags |= ORC_FLAG_NONFINITE;
     if (!eos_domain_ok(p, s)) flags |= ORC_FLAG_EOS_DOMAIN;
@@ -469,18 +552,46 @@ static unsigned fields_and_forces(const orc_params *p, const double *f,
 
 /* Total force at node n (R6) and, for the pseudopotential, K = |F_int|^2/psi^2
  * evaluated as G^2 |S|^2 (R3). */
+/* x component of the body force at node n: the constant fx plus the drive
+ * of R8. */
+static double body_fx(const orc_params *p, const orc_work *w, size_t n) {
+  if (p->ax == 0.0) return p->fx;
+  int x = (int)(n % (size_t)p->nx);
+  double a = (x <= p->x_split) ? p->ax : -p->ax;
+  return p->fx + a * fabs(w->rho[n] - p->rho_ave);
+}
+
 static void node_force(const orc_params *p, const orc_work *w, size_t n,
                        double *Fx, double *Fy, double *K) {
   if (p->model == ORC_MODEL_P) {
     double fxi = -G * w->psi[n] * w->Sx[n]; /* Eq. 10 */
     double fyi = -G * w->psi[n] * w->Sy[n];
     *K = G * G * (w->Sx[n] * w->Sx[n] + w->Sy[n] * w->Sy[n]);
-    *Fx = fxi + p->fx;
+    *Fx = fxi + body_fx(p, w, n);
     *Fy = fyi + p->fy;
   } else {
-    *Fx = -w->rho[n] * w->gmx[n] + p->fx; /* F = -rho grad(mu) */
+    *Fx = -w->rho[n] * w->gmx[n] + body_fx(p, w, n); /* F = -rho grad(mu) */
     *Fy = -w->rho[n] * w->gmy[n] + p->fy;
     *K = 0.0;
+  }
+}
+
+/* Eq. 6b at every node (after fields_and_forces), wall closure included. */
+static void velocity_field(const orc_params *p, const double *f, orc_work *w) {
+  size_t N = (size_t)p->nx * p->ny;
+#pragma omp parallel for schedule(static)
+  for (size_t n = 0; n < N; ++n) {
+    double Fx, Fy, K, jx = 0.0, jy = 0.0, fn[9];
+    node_force(p, w, n, &Fx, &Fy, &K);
+    for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
+    int side = wall_side(p, (int)(n / (size_t)p->nx));
+    if (side) wall_close(fn, side, -0.5 * Fx, wall_jy(p));
+    for (int i = 0; i < 9; ++i) {
+      jx += fn[i] * CX[i];
+      jy += fn[i] * CY[i];
+    }
+    w->ux[n] = (jx + 0.5 * Fx) / w->rho[n];
+    w->uy[n] = (jy + 0.5 * Fy) / w->rho[n];
   }
 }
 
@@ -491,19 +602,11 @@ uint32_t orc_fields(const orc_params *p, const double *f, double *rho,
   orc_work w;
   work_alloc(&w, N);
   unsigned flags = fields_and_forces(p, f, &w);
+  velocity_field(p, f, &w);
   for (size_t n = 0; n < N; ++n) {
-    double Fx, Fy, K, jx = 0.0, jy = 0.0, fn[9];
-    node_force(p, &w, n, &Fx, &Fy, &K);
-    for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
-    int side = wall_side(p, (int)(n / (size_t)p->nx));
-    if (side) wall_close(fn, side, -0.5 * Fx, -0.5 * p->fy);
-    for (int i = 0; i < 9; ++i) {
-      jx += fn[i] * CX[i];
-      jy += fn[i] * CY[i];
-    }
     if (rho) rho[n] = w.rho[n];
-    if (ux) ux[n] = (jx + 0.5 * Fx) / w.rho[n];
-    if (uy) uy[n] = (jy + 0.5 * Fy) / w.rho[n];
+    if (ux) ux[n] = w.ux[n];
+    if (uy) uy[n] = w.uy[n];
   }
   work_free(&w);
   return flags;
@@ -519,7 +622,7 @@ static void collide_node(const orc_params *p, const double *f, size_t N,
   for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
   node_force(p, w, n, &Fx, &Fy, &K);
   int side = wall_side(p, (int)(n / (size_t)p->nx));
-  if (side) wall_close(fn, side, -0.5 * Fx, -0.5 * p->fy);
+  if (side) wall_close(fn, side, -0.5 * Fx, wall_jy(p));
 
   /* Eq. 6b. */
   double jx = 0.0, jy = 0.0;
@@ -553,9 +656,11 @@ static void collide_node(const orc_params *p, const double *f, size_t N,
     mC[7] = -(w->Qxx[n] - w->Qyy[n]) / tau[7];
     mC[8] = -w->Qxy[n] / tau[8];
   } else {
-    double Fi[9];
-    feq_well_balanced(rho, ux, uy, feq); /* Eq. 20 */
-    forcing_well_balanced(ux, uy, Fx, Fy, w->grx[n], w->gry[n], Fi); /* Eq. 21 */
+    double Fi[9], dn[4] = {0.0, 0.0, 0.0, 0.0};
+    if (p->A != 0.0)
+      for (int k = 0; k < 4; ++k) dn[k] = w->du[k][n];
+    feq_well_balanced(rho, ux, uy, 0.0, p->A, dn, feq); /* Eq. 20, p_g = 0 */
+    forcing_well_balanced(ux, uy, Fx, Fy, w->grx[n], w->gry[n], 0.0, Fi); /* Eq. 21 */
     mat_vec(MM, Fi, mF);
   }
 
@@ -582,6 +687,12 @@ uint32_t orc_step(const orc_params *p, double *f, int64_t nsteps) {
   unsigned flags = 0;
   for (int64_t s = 0; s < nsteps; ++s) {
     flags |= fields_and_forces(p, f, &w);
+    if (p->model == ORC_MODEL_FE && p->A != 0.0) {
+      /* S of Eq. 20 needs the velocity of this step at every node (R9) */
+      velocity_field(p, f, &w);
+      gradient_u(nx, ny, p->walls, w.ux, w.du[0], w.du[1]);
+      gradient_u(nx, ny, p->walls, w.uy, w.du[2], w.du[3]);
+    }
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {

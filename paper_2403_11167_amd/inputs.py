@@ -64,6 +64,15 @@ def droplet(nx: int, ny: int, rho_l: float, rho_v: float, radius: float,
     return 0.5 * (rho_l + rho_v) - 0.5 * (rho_l - rho_v) * np.tanh(2 * (r - radius) / width)
 
 
+def droplets(nx: int, ny: int, rho_l: float, rho_v: float, radius: float,
+             centres, width: float = 5.0) -> np.ndarray:
+    """Several droplets of the same radius (the collision of Sec. 5.4): the
+    pointwise maximum of the single-droplet tanh profiles centred at each
+    (cx, cy) of centres (no periodic images)."""
+    return np.max([droplet(nx, ny, rho_l, rho_v, radius, width, cx, cy) for cx, cy in centres],
+                  axis=0)
+
+
 def spinodal(nx: int, ny: int, rho_mean: float, amplitude: float = 0.01,
              seed: int = 3) -> np.ndarray:
     """rho = rho_mean (1 + amplitude U(-1, 1)), numpy default_rng(seed)."""

@@ -608,3 +608,104 @@ def test_plates_flow_converges_to_diffuse_solution(model):
         devs.append(np.abs(ux[:, 0] - ud).max() / ud.max())
     assert 3.0 < devs[0] / devs[1] < 5.0, devs
     assert devs[1] < (0.01 if model == oracle.MODEL_FE else 0.0025)
+
+
+# ---- droplet-collision drive (Sec. 5.4) ---------------------------------------
+@pytest.mark.parametrize("model", [oracle.MODEL_P, oracle.MODEL_FE])
+def test_collision_drive_momentum_budget(model):
+    """Sec. 5.4 drives two droplets together with F_x = a(x) |rho - rho_ave|,
+    a = +a_x for x <= 100 and -a_x beyond on a 200-wide box.  Collision and
+    streaming change the total momentum sum f c by exactly the total force
+    (the j rows of Eq. 1 relax to j + F), so from one state the step with
+    the drive and the step without differ in momentum by exactly the sum of
+    the drive, computed here from the density field: sign, split column and
+    magnitude pinned (bar 1e-8 of it, the rounding of the momentum sums;
+    moving the split by one column changes it by ~10 %).  Also rho_ave defaults to the
+    initial mean and the drive only acts from ax_from_step on."""
+    a = 0.25
+    T = 0.8 * th.critical(th.CS, a, 4.0, 1.0)[0]
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    nx, ny, ax = 60, 30, 5e-6
+    rho0 = inputs.droplets(nx, ny, rl, rv, 8.0, [(15.0, 15.0), (45.0, 15.0)])
+    tau = [1.0] * 9
+    kw = dict(kappa=0.5) if model == oracle.MODEL_FE else dict(kappa_p=1.0)
+    on = oracle.OracleParams(nx, ny, model, oracle.EOS_CS, a, 4.0, 1.0, T, tau=tau, ax=ax,
+                             x_split=30, ax_from_step=5, **kw)
+    off = oracle.OracleParams(nx, ny, model, oracle.EOS_CS, a, 4.0, 1.0, T, tau=tau, **kw)
+    s_on, s_off = oracle.Simulation(on, rho0), oracle.Simulation(off, rho0)
+    assert s_on.p.rho_ave == pytest.approx(rho0.mean(), rel=1e-15)
+    s_on.step(5)
+    s_off.step(5)
+    assert np.array_equal(s_on.f, s_off.f)  # no drive before step 5
+    s_on.step(3)
+    s_off.f[...] = s_on.f
+    rho = s_on.fields()[0]
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])[:, None, None]
+    p_before = float((s_on.f * cx).sum())
+    s_on.step(1)
+    s_off.step(1)
+    dp = float((s_on.f * cx).sum()) - float((s_off.f * cx).sum())
+    sign = np.where(np.arange(nx) <= 30, 1.0, -1.0)[None, :]
+    drive = float((ax * sign * np.abs(rho - rho0.mean())).sum())
+    assert abs(dp - drive) < 1e-8 * abs(drive)  # rounding of the momentum sums
+    assert abs(drive) > 1e-7 and abs(p_before) < 1.0
+
+
+# ---- free energy with A != 0 (Eq. 20, Eq. 23) ---------------------------------
+def test_fe_full_equilibrium_moments():
+    """Eq. 20 in full: its moments are rho, rho u and
+    rho u u + p_g I + rho c_s^2 A S (S = grad u + grad u^T), the second
+    moment that gives the viscosity of Eq. 23; it reduces to the A = 0,
+    p_g = 0 equilibrium used everywhere else.  Checked on random inputs
+    through the lattice sums, which a dropped term, a wrong c_s power or a
+    transposed gradient index would break."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        rho, ux, uy, pg, A = rng.uniform(0.05, 2.0), *rng.uniform(-0.1, 0.1, 2), \
+            rng.uniform(-0.5, 0.5), rng.uniform(-0.3, 0.3)
+        du = rng.uniform(-0.05, 0.05, 4)  # d_x u_x, d_y u_x, d_x u_y, d_y u_y
+        f = oracle.feq_fe_full(rho, ux, uy, pg, A, du)
+        S = np.array([[2 * du[0], du[1] + du[2]], [du[1] + du[2], 2 * du[3]]])
+        u = np.array([ux, uy])
+        assert abs(f.sum() - rho) < 1e-15
+        assert np.allclose([(f * CX).sum(), (f * CY).sum()], rho * u, atol=1e-16, rtol=0)
+        P = np.array([[(f * CX * CX).sum(), (f * CX * CY).sum()],
+                      [(f * CY * CX).sum(), (f * CY * CY).sum()]])
+        assert np.allclose(P, rho * np.outer(u, u) + pg * np.eye(2) + rho * A * S / 3,
+                           atol=1e-15, rtol=0)
+        assert np.allclose(oracle.feq_fe_full(rho, ux, uy, 0.0, 0.0, du),
+                           oracle.feq(oracle.MODEL_FE, rho, ux, uy), atol=1e-16, rtol=0)
+
+
+@pytest.mark.parametrize("A", [0.15, -0.2])
+def test_shear_wave_decay_with_viscosity_tuning_A(A):
+    """Eq. 23: with the viscosity-tuning parameter A the free-energy model's
+    kinematic viscosity is nu = c_s^2 (tau_nu - 1/2 - A).  A uniform liquid
+    shear wave u_x = U sin(k y) decays as exp(-nu k^2 t); the error is
+    O(k^2) (the Eq. 24 stencil on u adds sin(k)/k), so halving k divides it
+    by about four."""
+    a, b, R, T = cs_params(0.25, 0.7)
+    rl, _, _ = th.maxwell(th.CS, a, b, R, T)
+    tau_nu = 0.8
+    tau = [1.0, 0.9, 1.1, 1.0, 0.7, 1.0, 0.7, tau_nu, tau_nu]
+    nu_th = (tau_nu - 0.5 - A) / 3
+    errs = []
+    for ny in (64, 128):
+        nx, U = 4, 1e-4
+        p = oracle.OracleParams(nx, ny, oracle.MODEL_FE, oracle.EOS_CS, a, b, R, T, tau=tau,
+                                kappa=0.5, A=A)
+        k = 2 * math.pi / ny
+        y = np.arange(ny)[:, None] + np.zeros((1, nx))
+        ux0 = U * np.sin(k * y)
+        s = oracle.Simulation(p, inputs.uniform(nx, ny, rl), ux0=ux0, uy0=np.zeros_like(ux0))
+        nsteps = 400 * (ny // 64) ** 2
+        amps = []
+        for n in (0, nsteps):
+            s.step(n - s.t)
+            rho, ux, _ = s.fields()
+            amps.append((ux[:, 0] * np.sin(k * y[:, 0])).sum() * 2 / ny)
+        assert rho.max() - rho.min() < 1e-11
+        nu = math.log(amps[0] / amps[1]) / (k * k * nsteps)
+        errs.append(nu / nu_th - 1)
+    assert abs(errs[1]) < 2e-3, errs
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
