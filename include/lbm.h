@@ -68,6 +68,17 @@ typedef enum {
 typedef enum { LBM_MODEL_P = 0, LBM_MODEL_FE = 1 } lbm_model;
 typedef enum { LBM_EOS_VDW = 0, LBM_EOS_CS = 1 } lbm_eos;
 typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_precision;
+/* Boundary in y (x is always periodic).  LBM_BOUNDARY_WALLS puts no-slip
+ * walls of Zou and He on the rows y = 0 and y = ny - 1, as in the two-phase
+ * channel flow of Sec. 5.3: those rows are fluid nodes held at zero
+ * velocity (under Eq. 6b); the populations entering from outside are
+ * rebuilt each step, the normal one equal to its opposite and the two
+ * diagonal ones from the momentum -F/2 that u = 0 requires.  The density
+ * stencils (psi, mu, grad rho) see mirrored rows past a wall, so the
+ * density has no normal gradient there.  Needs ny >= 3 and fy = 0 (the
+ * closure conserves mass only without a force normal to the walls); single
+ * lattices only (a batch with walls returns LBM_ERR_UNSUPPORTED). */
+typedef enum { LBM_BOUNDARY_PERIODIC = 0, LBM_BOUNDARY_WALLS = 1 } lbm_boundary;
 
 /* Sticky device flags (lbm_obs.flags). */
 #define LBM_FLAG_NONFINITE 1u  /* a density became NaN or infinite          */
@@ -78,11 +89,11 @@ typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_precision;
 
 /* Problem statement (Sec. 2, Sec. 5).  Plain data; copied by lbm_init(). */
 typedef struct {
-  int32_t nx, ny;       /* periodic lattice, 1 <= nx, ny; nx * ny < 2^31   */
+  int32_t nx, ny;       /* lattice, 1 <= nx, ny; nx * ny < 2^31            */
   int32_t model;        /* lbm_model                                        */
   int32_t eos;          /* lbm_eos                                          */
   int32_t precision;    /* lbm_precision                                    */
-  int32_t reserved0;    /* must be 0                                        */
+  int32_t boundary;     /* lbm_boundary (y direction; x is periodic)         */
   double a, b, R, T;    /* EOS constants and absolute temperature (> 0)     */
   double tau[9];        /* relaxation time of each moment row of M (Eq. 3,
                            order rho, e, zeta, j_x, q_x, j_y, q_y, p_xx,
@@ -92,8 +103,14 @@ typedef struct {
   double kappa_li;      /* P: surface-tension coefficient kappa^Li (Eq. 30) */
   double kappa_p;       /* P: interface-width coefficient kappa^P (Eq. 30-32) */
   double kappa;         /* FE: gradient coefficient kappa (Sec. 2.2), >= 0  */
-  double A;             /* FE: viscosity-tuning A of Eq. 20; must be 0      */
-  double fx, fy;        /* constant body force added to the model force     */
+  double A;             /* FE: viscosity-tuning A of Eq. 20 (nu = c_s^2
+                           (tau[7] - 1/2 - A) > 0, Eq. 23).  A != 0 forms
+                           the velocity field of each step before the step
+                           (S = grad u + grad u^T with the Eq. 24 stencil;
+                           past a wall u is reflected with its sign flipped);
+                           P: LBM_ERR_UNSUPPORTED; batches: unsupported    */
+  double fx, fy;        /* constant body force added to the model force
+                           (with walls fy must be 0: LBM_ERR_UNSUPPORTED)  */
   double rho_ref;       /* FP32_SHIFTED: reference density of the storage
                            shift (<= 0: the smallest initial density)       */
   /* Launch shape; 0 selects the tuned default (see lbm_autotune).  Results
@@ -102,8 +119,18 @@ typedef struct {
   int32_t tile_y;       /* rows per workgroup segment: 1 .. 1024, or 0: set at
                            the first step so that the tiles fill whole rounds
                            of resident workgroups (at least 16 rows)        */
-  int32_t kernel_flags; /* 0, or LBM_KF_SET | any of the LBM_KF_* below      */
-  int32_t reserved1;    /* must be 0                                        */
+  int32_t kernel_flags; /* 0, or LBM_KF_SET | any of the LBM_KF_* below
+                           (with walls: ignored, non-temporal stores only) */
+  /* Droplet-collision drive (Sec. 5.4): an x force a(x) |rho - rho_ave|
+     added to fx, with a = +ax for x <= x_split and -ax beyond, in the steps
+     that start at t >= ax_from_step (the paper: a_x = 5e-6, x_split = 100 on
+     a 200-wide box, from t = 2000).  ax = 0 turns it off.  Periodic
+     lattices and single lattices only (batches: LBM_ERR_UNSUPPORTED). */
+  int32_t x_split;
+  double ax;
+  double rho_ave;       /* <= 0: the mean of the initial density (the scheme
+                           conserves mass, so the mean stays constant)      */
+  int64_t ax_from_step; /* >= 0                                              */
 } lbm_params;
 
 #define LBM_KF_SET 0x80000000u  /* kernel_flags given explicitly            */
@@ -157,7 +184,9 @@ lbm_status lbm_observe(lbm_ctx* ctx, int32_t cx, int32_t cy, lbm_obs* out,
 
 /* Copy the current post-streaming populations f_i(x, t) into d_f (device,
  * 9*nx*ny doubles, plane i at offset i*nx*ny) / overwrite the state from
- * d_f (checkpoint and resume).  Asynchronous. */
+ * d_f (checkpoint and resume).  With walls, the entries of the populations
+ * that enter a wall row from outside are unspecified (the next step rebuilds
+ * them), so a get / set round trip still resumes exactly.  Asynchronous. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* d_f);
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* d_f);
 
@@ -193,7 +222,8 @@ typedef struct lbm_batch lbm_batch;
 
 lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, size_t* bytes);
 
-/* p: host array of n problems (common precision); d_rho0: host array of n
+/* p: host array of n problems (common precision, periodic boundaries:
+ * LBM_BOUNDARY_WALLS returns LBM_ERR_UNSUPPORTED); d_rho0: host array of n
  * device pointers to each problem's initial density (nx*ny doubles). */
 lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const* d_rho0,
                             void* d_workspace, size_t bytes, void* hip_stream,

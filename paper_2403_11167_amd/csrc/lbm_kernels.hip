@@ -55,6 +55,8 @@ struct KParams {
   int xcd_remap;  // 1: map workgroups so that each XCD gets a contiguous
                   // band of tiles (neighbouring tiles share its L2)
   int rowpitch;   // population elements per lattice row (576 per 64 columns)
+  int walls;      // 1: no-slip walls on the rows y = 0 and ny - 1 (observation
+                  // kernels; the step kernels take it as a template argument)
   C a, b, RT;
   C lam_e, lam_z, lam_q, lam_nu;  // 1/tau of the e, zeta, q, p rows (Eq. 3)
   C hl_e, hl_z, hl_q, hl_nu;      // 1 - lam/2 (Eq. 1 forcing factor)
@@ -62,6 +64,11 @@ struct KParams {
   C qa, qb;        // P: Q tensor coefficients, see q_terms()
   C kappa;         // FE
   C fx, fy;        // constant body force
+  C ax, rho_ave;   // droplet-collision drive a(x) |rho - rho_ave| (0: off now)
+  int x_split;     // a = +ax for x <= x_split, -ax beyond
+  C A;             // FE: viscosity-tuning A of Eq. 20 (0: off)
+  const double* uax;  // FE with A != 0: velocity field of the current step
+  const double* uay;
   C rho_ref;       // sum of the storage shift s_i
   C s0, sax, sdg;  // storage shift for i = 0, axis and diagonal velocities
   // Reference terms for chemical-potential differences (shifted storage):
@@ -271,10 +278,13 @@ __device__ __forceinline__ void gather(const C* bot, const C* mid, const C* top,
 // with M the moment matrix of Eq. 48, M^-1 of Eq. 49 applied in factored
 // form, m^eq of Eq. 4 (P) or Eq. 20 (FE), mF of Eq. 32 (P) or the moments of
 // Eq. 21 (FE), mC of Eq. 13 (P).  The j rows reduce exactly to j + F.
-template <int MODEL, class C>
+// With AV = 1 (free energy) the equilibrium also carries the A terms of
+// Eq. 20: a_div = rho A div(u) and a_xx, a_xy, their p_xx and p_xy moments.
+template <int MODEL, int AV = 0, class C>
 __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
                                         C t0, C t1, C t2, C t3,
-                                        const KParams<C>& kp, C& ux_out, C& uy_out) {
+                                        const KParams<C>& kp, C& ux_out, C& uy_out,
+                                        C a_div = C(0), C a_xx = C(0), C a_xy = C(0)) {
   // P: t0 = G^2 |S|^2, t1 = Qxx + Qyy, t2 = Qxx - Qyy, t3 = Qxy.
   // FE: t0 = d_x rho, t1 = d_y rho.
   C jx = (g[1] - g[3]) + ((g[5] - g[7]) - (g[6] - g[8]));
@@ -308,6 +318,15 @@ __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
   C eqqx = -rho * ux, eqqy = -rho * uy;
   C eqpxx = rho * (ux * ux - uy * uy);
   C eqpxy = rho * ux * uy;
+  if constexpr (AV != 0) {
+    // moments of w_i rho (c c - c_s^2 I) : c_s^2 A S / (2 c_s^4) and of the
+    // rest term -w_0 rho A div(u): e 2 rho A div u, zeta -2 rho A div u,
+    // p_xx (2/3) rho A (d_x u_x - d_y u_y), p_xy (1/3) rho A (d_x u_y + d_y u_x)
+    eqe += C(2) * a_div;
+    eqz -= C(2) * a_div;
+    eqpxx += a_xx;
+    eqpxy += a_xy;
+  }
 
   C uF = ux * Fx + uy * Fy;
   C Fe, Fz, Fpxx, Fpxy;
@@ -394,6 +413,55 @@ __device__ __forceinline__ int wrapi(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
+// ---- no-slip walls (Sec. 5.3) -----------------------------------------------
+// Rows y = 0 and ny - 1 are wall rows: fluid nodes held at u = 0 by the
+// closure of Zou and He.  Past a wall the density stencils see the mirror
+// image of the rows inside.
+__device__ __forceinline__ int seen_row(int y, int ny) {
+  return y < 0 ? -y : (y > ny - 1 ? 2 * (ny - 1) - y : y);
+}
+
+// +1 on the bottom wall row (the populations with c_y = +1 arrive from
+// outside), -1 on the top one, 0 elsewhere.
+__device__ __forceinline__ int wall_side(int y, int ny) {
+  return y == 0 ? 1 : (y == ny - 1 ? -1 : 0);
+}
+
+// The closure in two parts.  A wall node must carry sum_i g_i c_i =
+// (jx, jy) = -F/2 so that Eq. 6b gives u = 0; the normal unknown equals its
+// opposite (non-equilibrium bounce-back at zero wall velocity) and the two
+// diagonal unknowns take the rest.  wall_fill applies jy = -fy/2 with
+// jx = 0: the diagonal pair's sum, hence the density, does not depend on jx.
+// wall_fx adds the jx = -Fx/2 part once the tangential force is known.  The
+// deviations g = f - s obey the same relations since the shift s is
+// symmetric under c -> -c.
+template <class C>
+__device__ __forceinline__ void wall_fill(C g[9], int side, C fy) {
+  const C t = C(0.5) * (g[1] - g[3]);
+  const C h = C(-0.25) * fy;  // jy / 2
+  if (side > 0) {
+    g[2] = g[4];
+    g[5] = g[7] - t + h;
+    g[6] = g[8] + t + h;
+  } else {
+    g[4] = g[2];
+    g[7] = g[5] + t - h;
+    g[8] = g[6] - t - h;
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void wall_fx(C g[9], int side, C Fx) {
+  const C q = C(0.25) * Fx;  // -jx / 2
+  if (side > 0) {
+    g[5] -= q;
+    g[6] += q;
+  } else {
+    g[7] += q;
+    g[8] -= q;
+  }
+}
+
 // ---- per-tile step bodies -------------------------------------------------
 // One workgroup of BX threads updates the tile [x0, x0 + BX) x [y0, y0 + LY)
 // of one lattice (clipped to the lattice).  The single-lattice kernels and
@@ -441,8 +509,47 @@ __device__ __forceinline__ void chk_commit(const ChkOut<C>& ck, C dmax, double* 
   }
 }
 
-// Pseudopotential step on one tile.
-template <int EOS, class S, class C, int BX, int NT, int CHK>
+// Eq. 24 gradient at (x, y) of a velocity component held in global memory
+// (the A term of Eq. 20).  Past a wall the mirrored row enters with its sign
+// flipped, so the velocity vanishes on the wall row as the closure imposes.
+template <class C>
+__device__ __forceinline__ void grad_u(const double* __restrict__ u, int nx, int ny,
+                                       int walls, int x, int y, C& gx, C& gy) {
+  const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+  int ym = wrapi(y - 1, ny), yp = wrapi(y + 1, ny);
+  C sm = C(1), sp = C(1);
+  if (walls) {
+    if (y == 0) { ym = 1; sm = C(-1); }
+    if (y == ny - 1) { yp = ny - 2; sp = C(-1); }
+  }
+  const double* r0 = u + (size_t)y * nx;
+  const double* rm = u + (size_t)ym * nx;
+  const double* rp = u + (size_t)yp * nx;
+  C v[9];
+  v[0] = (C)r0[x];
+  v[1] = (C)r0[xp];
+  v[2] = sp * (C)rp[x];
+  v[3] = (C)r0[xm];
+  v[4] = sm * (C)rm[x];
+  v[5] = sp * (C)rp[xp];
+  v[6] = sp * (C)rp[xm];
+  v[7] = sm * (C)rm[xm];
+  v[8] = sm * (C)rm[xp];
+  grad_sum(v, gx, gy);
+}
+
+// x force of the droplet-collision drive at column x (Sec. 5.4).
+template <class C>
+__device__ __forceinline__ C drive_fx(const KParams<C>& kp, int x, C rho) {
+  C d = rho - kp.rho_ave;
+  d = d < C(0) ? -d : d;
+  return (x <= kp.x_split ? kp.ax : -kp.ax) * d;
+}
+
+// Pseudopotential step on one tile.  GEN = 1: the general kernel, which
+// also takes the options switched at run time -- no-slip walls in y
+// (Sec. 5.3, kp.walls) and the droplet-collision drive (Sec. 5.4, kp.ax).
+template <int EOS, class S, class C, int BX, int NT, int CHK, int GEN = 0>
 __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict__ dst,
                                        const KParams<C>& kp, unsigned* __restrict__ flags,
                                        int x0, int y0, const ChkOut<C>& ck) {
@@ -473,14 +580,26 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
   C drho_c = C(0), drho_n = C(0);
 
   auto rowoff = [&](int y) { return wrapi(y, ny) * kp.rowpitch; };
+  // row whose populations give the potential seen at row y, and its wall side
+  auto seen = [&](int y) {
+    if constexpr (GEN != 0) return kp.walls ? seen_row(y, ny) : y;
+    else return y;
+  };
+  auto close = [&](int ys, C g[9]) {
+    if constexpr (GEN != 0) {
+      const int sd = kp.walls ? wall_side(ys, ny) : 0;
+      if (sd) wall_fill(g, sd, kp.fy);
+    }
+  };
 
   // Rows y0-1 (psi only) and y0 (psi and populations).
   for (int r = 0; r < 2; ++r) {
-    const int y = y0 - 1 + r;
+    const int y = seen(y0 - 1 + r);
     const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
     if (active) {
       C g[9];
       pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
+      close(y, g);
       C dr = sum9(g);
       C rho = kp.rho_ref + dr;
       fl |= domain_flags<MODEL_P, EOS>(rho, kp);
@@ -493,6 +612,7 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
     if (hl) {
       C g[9];
       pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, g);
+      close(y, g);
       C rho = kp.rho_ref + sum9(g);
       psi_s[r][hj] = psi_of<EOS>(rho, kp, fl);
     }
@@ -502,11 +622,12 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
     const int y = y0 + k;
     // pull row y+1 into the ring
     {
-      const int yn = y + 1;
+      const int yn = seen(y + 1);
       const int r0 = rowoff(yn), rm = rowoff(yn - 1), rp = rowoff(yn + 1);
       C* row = psi_s[(k + 2) & 3];
       if (active) {
         pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, gn);
+        close(yn, gn);
         drho_n = sum9(gn);
         C rho = kp.rho_ref + drho_n;
         fl |= domain_flags<MODEL_P, EOS>(rho, kp);
@@ -515,6 +636,7 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
       if (hl) {
         C g[9];
         pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, g);
+        close(yn, g);
         C rho = kp.rho_ref + sum9(g);
         row[hj] = psi_of<EOS>(rho, kp, fl);
       }
@@ -532,6 +654,12 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
       C qs, qd, qxy;
       q_terms(v, kp.qa, kp.qb, qs, qd, qxy);
       C rho = kp.rho_ref + drho_c;
+      if constexpr (GEN != 0) {
+        if (kp.ax != C(0)) Fx += drive_fx(kp, x, rho);
+        // the mirrored rows make S_y exactly zero on a wall row, so Fy = fy
+        const int sd = kp.walls ? wall_side(y, ny) : 0;
+        if (sd) wall_fx(gc, sd, Fx);
+      }
       C ux, uy;
       collide<MODEL_P>(gc, drho_c, rho, Fx, Fy, K, qs, qd, qxy, kp, ux, uy);
       chk_node<CHK>(ck, y * nx + x, ux, uy, dmax);
@@ -654,8 +782,9 @@ __device__ __forceinline__ void tile_p_pipe(const S* __restrict__ src, S* __rest
   commit_flags(fl, flags, &s_flag);
 }
 
-// Free-energy step on one tile.
-template <int EOS, class S, class C, int BX, int NT, int CHK>
+// Free-energy step on one tile.  GEN as for tile_p, plus the A term of
+// Eq. 20 (kp.A).
+template <int EOS, class S, class C, int BX, int NT, int CHK, int GEN = 0>
 __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict__ dst,
                                         const KParams<C>& kp, unsigned* __restrict__ flags,
                                         int x0, int y0, const ChkOut<C>& ck) {
@@ -694,11 +823,20 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
 
   // density deviation of row y into ring slot r (and the populations of
   // interior lanes)
-  auto load_row = [&](int y, int slot, C g[9], C& dr) {
+  auto load_row = [&](int yr, int slot, C g[9], C& dr) {
+    int y = yr;
+    int sd = 0;
+    if constexpr (GEN != 0) {
+      if (kp.walls) {
+        y = seen_row(yr, ny);  // past a wall: the mirrored row's density
+        sd = wall_side(y, ny);
+      }
+    }
     const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
     C* row = rho_s[slot & 7];
     if (active) {
       pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
+      if (GEN != 0 && sd) wall_fill(g, sd, kp.fy);
       dr = sum9(g);
       fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dr, kp);
       row[t + 2] = dr;
@@ -706,6 +844,7 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
     if (hr) {
       C h[9];
       pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
+      if (GEN != 0 && sd) wall_fill(h, sd, kp.fy);
       row[hj] = sum9(h);
     }
   };
@@ -758,7 +897,31 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
       C Fx = -rho * gmx + kp.fx;  // F = -rho grad(mu)
       C Fy = -rho * gmy + kp.fy;
       C ux, uy;
-      collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
+      if constexpr (GEN != 0) {
+        if (kp.ax != C(0)) Fx += drive_fx(kp, x, rho);
+        // on a wall row the mirrored rows give d_y rho = d_y mu = 0 (set
+        // exactly: the two sides of the mirror round differently)
+        const int sd = kp.walls ? wall_side(y, ny) : 0;
+        if (sd) {
+          Fy = kp.fy;
+          gry = C(0);
+          wall_fx(g0, sd, Fx);
+        }
+        C a_div = C(0), a_xx = C(0), a_xy = C(0);
+        if (kp.A != C(0)) {
+          C dxux, dyux, dxuy, dyuy;
+          grad_u(kp.uax, nx, ny, kp.walls, x, y, dxux, dyux);
+          grad_u(kp.uay, nx, ny, kp.walls, x, y, dxuy, dyuy);
+          const C ra = rho * kp.A;
+          a_div = ra * (dxux + dyuy);
+          a_xx = C(2.0 / 3.0) * ra * (dxux - dyuy);
+          a_xy = C(1.0 / 3.0) * ra * (dxuy + dyux);
+        }
+        collide<MODEL_FE, 1>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy, a_div,
+                             a_xx, a_xy);
+      } else {
+        collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
+      }
       chk_node<CHK>(ck, y * nx + x, ux, uy, dmax);
       const int off = y * kp.rowpitch + c0;
 #pragma unroll
@@ -914,13 +1077,14 @@ __device__ __forceinline__ void tile_fe_pipe(const S* __restrict__ src, S* __res
 }
 
 // ---- single-lattice step kernels --------------------------------------------
-template <int EOS, class S, class C, int BX, int NT, int WPE>
+template <int EOS, class S, class C, int BX, int NT, int WPE, int GEN = 0>
 __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 void k_step_p(const S* __restrict__ src, S* __restrict__ dst, const KParams<C> kp,
               unsigned* __restrict__ flags) {
   const int tile = tile_index(kp.xcd_remap);
-  tile_p<EOS, S, C, BX, NT, 0>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
-                               (tile / kp.nstrips) * kp.LY, ChkOut<C>{nullptr, nullptr, nullptr});
+  tile_p<EOS, S, C, BX, NT, 0, GEN>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
+                                   (tile / kp.nstrips) * kp.LY,
+                                   ChkOut<C>{nullptr, nullptr, nullptr});
 }
 
 template <int EOS, class S, class C, int BX, int NT, int WPE>
@@ -932,13 +1096,14 @@ void k_step_p_pipe(const S* __restrict__ src, S* __restrict__ dst, const KParams
                                  (tile / kp.nstrips) * kp.LY);
 }
 
-template <int EOS, class S, class C, int BX, int NT, int WPE>
+template <int EOS, class S, class C, int BX, int NT, int WPE, int GEN = 0>
 __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 void k_step_fe(const S* __restrict__ src, S* __restrict__ dst, const KParams<C> kp,
                unsigned* __restrict__ flags) {
   const int tile = tile_index(kp.xcd_remap);
-  tile_fe<EOS, S, C, BX, NT, 0>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
-                                (tile / kp.nstrips) * kp.LY, ChkOut<C>{nullptr, nullptr, nullptr});
+  tile_fe<EOS, S, C, BX, NT, 0, GEN>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
+                                    (tile / kp.nstrips) * kp.LY,
+                                    ChkOut<C>{nullptr, nullptr, nullptr});
 }
 
 template <int EOS, class S, class C, int BX, int NT, int WPE>
@@ -1070,6 +1235,8 @@ __global__ void k_obs_rho(const S* __restrict__ src, const KParams<double> kp,
     int r0 = y * rw, rm = wrapi(y - 1, ny) * rw, rp = wrapi(y + 1, ny) * rw;
     double g[9];
     pull9(src, rm, r0, rp, colo(xm), colo(x), colo(xp), g);
+    const int sd = kp.walls ? wall_side(y, ny) : 0;
+    if (sd) wall_fill(g, sd, kp.fy);
     double rho = kp.rho_ref + sum9(g);
     fl |= domain_flags<MODEL, EOS>(rho, kp);
     rho_w[n] = rho;
@@ -1080,9 +1247,11 @@ __global__ void k_obs_rho(const S* __restrict__ src, const KParams<double> kp,
 
 template <class C>
 __device__ __forceinline__ void gather_global(const C* __restrict__ a, int nx,
-                                              int ny, int x, int y, C v[9]) {
+                                              int ny, int walls, int x, int y, C v[9]) {
   int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
-  int r0 = y * nx, rm = wrapi(y - 1, ny) * nx, rp = wrapi(y + 1, ny) * nx;
+  int ym = (walls && y == 0) ? 1 : wrapi(y - 1, ny);        // mirrored past a wall
+  int yp = (walls && y == ny - 1) ? ny - 2 : wrapi(y + 1, ny);
+  int r0 = y * nx, rm = ym * nx, rp = yp * nx;
   v[0] = a[r0 + x];
   v[1] = a[r0 + xp];
   v[2] = a[rp + x];
@@ -1104,7 +1273,7 @@ __global__ void k_obs_mu(const KParams<double> kp, const double* __restrict__ rh
        n += (size_t)gridDim.x * blockDim.x) {
     int x = (int)(n % nx), y = (int)(n / nx);
     double v[9];
-    gather_global(rho_w, nx, ny, x, y, v);
+    gather_global(rho_w, nx, ny, kp.walls, x, y, v);
     aux_w[n] = eos_mu<EOS>(v[0], kp) - kp.kappa * lap9(v);
   }
 }
@@ -1138,20 +1307,27 @@ __global__ __launch_bounds__(NT) void k_obs_u(
     int r0 = y * rw, rm = wrapi(y - 1, ny) * rw, rp = wrapi(y + 1, ny) * rw;
     double g[9];
     pull9(src, rm, r0, rp, colo(xm), colo(x), colo(xp), g);
+    const int sd = kp.walls ? wall_side(y, ny) : 0;
+    if (sd) wall_fill(g, sd, kp.fy);
     double rho = rho_w[n];
     double Fx, Fy;
     if (MODEL == MODEL_P) {
       double v[9], sx, sy;
-      gather_global(aux_w, nx, ny, x, y, v);
+      gather_global(aux_w, nx, ny, kp.walls, x, y, v);
       grad_sum(v, sx, sy);
       Fx = v[0] * sx + kp.fx;
       Fy = v[0] * sy + kp.fy;
     } else {
       double v[9], sx, sy;
-      gather_global(aux_w, nx, ny, x, y, v);
+      gather_global(aux_w, nx, ny, kp.walls, x, y, v);
       grad_sum(v, sx, sy);
       Fx = -rho * sx + kp.fx;  // F = -rho grad(mu), Eq. 24 gradient
       Fy = -rho * sy + kp.fy;
+    }
+    if (kp.ax != 0.0) Fx += drive_fx(kp, x, rho);
+    if (sd) {
+      Fy = kp.fy;  // zero normal interaction force on a wall row
+      wall_fx(g, sd, Fx);
     }
     double jx = (g[1] - g[3]) + ((g[5] - g[7]) - (g[6] - g[8]));
     double jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
@@ -1279,7 +1455,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t row_pitch(int nx) { return (size_t)576 * (size_t)((nx + 63) / 64); }
 
 struct Layout {
-  size_t pop_bytes, fA, fB, rho_w, aux_w, uxp, uyp, part, flags, result, total;
+  size_t pop_bytes, fA, fB, rho_w, aux_w, uxp, uyp, uax, uay, part, flags, result, total;
   int obs_blocks;
 };
 
@@ -1295,6 +1471,10 @@ Layout make_layout(const lbm_params* p) {
   L.aux_w = off; off += align_up(N * 8);
   L.uxp = off; off += align_up(N * 8);
   L.uyp = off; off += align_up(N * 8);
+  // FE with A != 0: the velocity field of the current step
+  const size_t ua = (p->model == LBM_MODEL_FE && p->A != 0.0) ? align_up(N * 8) : 0;
+  L.uax = off; off += ua;
+  L.uay = off; off += ua;
   L.obs_blocks = (int)std::min<size_t>((N + kObsThreads - 1) / kObsThreads, kObsBlocksMax);
   L.part = off; off += align_up((size_t)L.obs_blocks * sizeof(ObsPartial));
   L.flags = off; off += kAlign;
@@ -1314,7 +1494,9 @@ lbm_status validate(const lbm_params* p) {
   if (p->model != LBM_MODEL_P && p->model != LBM_MODEL_FE) return LBM_ERR_INVALID_ARG;
   if (p->eos != LBM_EOS_VDW && p->eos != LBM_EOS_CS) return LBM_ERR_INVALID_ARG;
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED) return LBM_ERR_INVALID_ARG;
-  if (p->reserved0 != 0) return LBM_ERR_INVALID_ARG;
+  if (p->boundary != LBM_BOUNDARY_PERIODIC && p->boundary != LBM_BOUNDARY_WALLS)
+    return LBM_ERR_INVALID_ARG;
+  if (p->boundary == LBM_BOUNDARY_WALLS && p->ny < 3) return LBM_ERR_INVALID_ARG;
   if (!finite(p->a) || !finite(p->b) || !finite(p->R) || !finite(p->T)) return LBM_ERR_INVALID_ARG;
   if (p->a < 0 || p->b <= 0 || p->R <= 0 || p->T <= 0) return LBM_ERR_INVALID_ARG;
   for (int i = 0; i < 9; ++i)
@@ -1326,7 +1508,14 @@ lbm_status validate(const lbm_params* p) {
       !finite(p->rho_ref))
     return LBM_ERR_INVALID_ARG;
   if (p->model == LBM_MODEL_FE && p->kappa < 0) return LBM_ERR_INVALID_ARG;
-  if (p->A != 0.0) return LBM_ERR_UNSUPPORTED;
+  if (p->A != 0.0) {
+    // Eq. 23: nu = c_s^2 (tau_nu - 1/2 - A) must stay positive; FE only
+    if (p->model != LBM_MODEL_FE) return LBM_ERR_UNSUPPORTED;
+    if (!(p->tau[7] - 0.5 - p->A > 0.0)) return LBM_ERR_INVALID_ARG;
+  }
+  // Zou-He walls hold u = 0 under a tangential force only: with a normal
+  // body force the closure does not conserve mass
+  if (p->boundary == LBM_BOUNDARY_WALLS && p->fy != 0.0) return LBM_ERR_UNSUPPORTED;
   return LBM_OK;
 }
 
@@ -1337,6 +1526,7 @@ KParams<C> make_kparams(const lbm_params* p, double rho_ref, int nstrips,
   k.nx = p->nx;
   k.ny = p->ny;
   k.rowpitch = (int)row_pitch(p->nx);
+  k.walls = p->boundary == LBM_BOUNDARY_WALLS ? 1 : 0;
   k.nstrips = nstrips;
   k.nseg = nseg;
   k.LY = LY;
@@ -1368,6 +1558,10 @@ KParams<C> make_kparams(const lbm_params* p, double rho_ref, int nstrips,
   k.kappa = (C)p->kappa;
   k.fx = (C)p->fx;
   k.fy = (C)p->fy;
+  k.ax = (C)0;  // the drive is switched on per step (set_drive)
+  k.x_split = p->x_split;
+  k.A = (C)p->A;
+  k.uax = k.uay = nullptr;
   // rho_ref is chosen by lbm_init so that every shift value below is exact
   // in float and M s is exact (rho_ref = 36 q for P with q a short float).
   double s0, sax, sdg;
@@ -1417,6 +1611,7 @@ struct lbm_ctx {
   int64_t step;
   int have_prev;
   double rho_ref;  // storage shift reference (0 for FP64)
+  double rho_ave;  // mean initial density (collision drive)
   LaunchCfg lc;
   int nstrips, nseg, xcd_remap;
   KParams<double> kd;
@@ -1452,6 +1647,13 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     // (in FP64 its four live population rows cost a wave of occupancy)
     lc.pipe = env_int("LBM_PIPE", (p->model == LBM_MODEL_P || !fp64) ? 1 : 0) ? 1 : 0;
   }
+  if (p->boundary == LBM_BOUNDARY_WALLS || p->ax != 0.0 || p->A != 0.0) {
+    // walls, the collision drive and A != 0 run in the general kernel:
+    // plain row loop, non-temporal stores
+    lc.nt = 1;
+    lc.wpe = 0;
+    lc.pipe = 0;
+  }
   int nstrips = (p->nx + lc.bx - 1) / lc.bx;
   int LY = p->tile_y ? p->tile_y : env_int("LBM_LY", 0);
   lc.auto_ly = (LY <= 0 && env_int("LBM_ROUNDS", 1) > 0) ? 1 : 0;
@@ -1471,7 +1673,8 @@ lbm_status validate_launch(const lbm_params* p) {
   if (p->tile_x != 0 && p->tile_x != 64 && p->tile_x != 256) return LBM_ERR_INVALID_ARG;
   if (p->tile_y < 0 || p->tile_y > 1024) return LBM_ERR_INVALID_ARG;
   if (p->kernel_flags != 0 && !((unsigned)p->kernel_flags & LBM_KF_SET)) return LBM_ERR_INVALID_ARG;
-  if (p->reserved1 != 0) return LBM_ERR_INVALID_ARG;
+  if (!std::isfinite(p->ax) || !std::isfinite(p->rho_ave) || p->ax_from_step < 0)
+    return LBM_ERR_INVALID_ARG;
   return LBM_OK;
 }
 
@@ -1542,8 +1745,59 @@ void launch_step_w(lbm_ctx* c, const KParams<C>& kp) {
   c->cur ^= 1;
 }
 
+int grid1d(size_t N) {
+  size_t b = (N + 255) / 256;
+  return (int)std::min<size_t>(std::max<size_t>(b, 1), 4096);
+}
+
+// The general kernel (walls of Sec. 5.3, the droplet-collision drive of
+// Sec. 5.4, the A term of Eq. 20): plain row loop, no register cap,
+// non-temporal stores.  With A != 0 the velocity field of the step is
+// formed first by the observation passes (Eq. 6b at every node), because
+// S = grad u + grad u^T needs the neighbours' velocities.
+template <int MODEL, int EOS, class S, class C, int BX>
+void launch_step_gen(lbm_ctx* c, const KParams<C>& kp) {
+  if (c->lc.auto_ly) {
+    if constexpr (MODEL == MODEL_P) tune_ly(c, k_step_p<EOS, S, C, BX, 1, 0, 1>, BX);
+    else tune_ly(c, k_step_fe<EOS, S, C, BX, 1, 0, 1>, BX);
+  }
+  const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
+  S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
+  unsigned* flags = (unsigned*)(c->ws + c->L.flags);
+  if constexpr (MODEL == MODEL_FE) {
+    if (c->p.A != 0.0) {
+      double* rho_w = (double*)(c->ws + c->L.rho_w);
+      double* aux_w = (double*)(c->ws + c->L.aux_w);
+      size_t N = (size_t)c->p.nx * c->p.ny;
+      hipLaunchKernelGGL((k_obs_rho<MODEL_FE, EOS, S>), dim3(grid1d(N)), dim3(256), 0, c->stream,
+                         src, c->kd, rho_w, aux_w, flags);
+      hipLaunchKernelGGL((k_obs_mu<EOS>), dim3(grid1d(N)), dim3(256), 0, c->stream, c->kd,
+                         (const double*)rho_w, aux_w);
+      hipLaunchKernelGGL((k_obs_u<MODEL_FE, S, kObsThreads>), dim3(c->L.obs_blocks),
+                         dim3(kObsThreads), 0, c->stream, src, c->kd, (const double*)rho_w,
+                         (const double*)aux_w, (double*)nullptr, (double*)nullptr,
+                         (double*)nullptr, (double*)(c->ws + c->L.uax),
+                         (double*)(c->ws + c->L.uay), 0, (ObsPartial*)(c->ws + c->L.part));
+    }
+  }
+  dim3 grid(c->nstrips * c->nseg), block(BX);
+  if constexpr (MODEL == MODEL_P)
+    hipLaunchKernelGGL((k_step_p<EOS, S, C, BX, 1, 0, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
+  else
+    hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, 1, 0, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
+  c->cur ^= 1;
+}
+
+bool needs_gen(const lbm_params& p) {
+  return p.boundary == LBM_BOUNDARY_WALLS || p.ax != 0.0 || p.A != 0.0;
+}
+
 template <int MODEL, int EOS, class S, class C, int BX>
 void launch_step_bx(lbm_ctx* c, const KParams<C>& kp) {
+  if (needs_gen(c->p)) {
+    launch_step_gen<MODEL, EOS, S, C, BX>(c, kp);
+    return;
+  }
   constexpr int W = wpe_target<MODEL, S>();
   if (c->lc.nt) {
     if (c->lc.wpe) launch_step_w<MODEL, EOS, S, C, BX, 1, W>(c, kp);
@@ -1578,10 +1832,6 @@ void step_once(lbm_ctx* c) {
   }
 }
 
-int grid1d(size_t N) {
-  size_t b = (N + 255) / 256;
-  return (int)std::min<size_t>(std::max<size_t>(b, 1), 4096);
-}
 
 template <class S>
 void launch_init(lbm_ctx* c, const double* rho0) {
@@ -1650,6 +1900,16 @@ lbm_status ctx_setup(const lbm_params* p, void* d_workspace, const double* d_rho
   c->step = 0;
   c->have_prev = 0;
   c->rho_ref = 0.0;
+  {
+    // mean initial density for the collision drive: compensated sum
+    double s = 0.0, e = 0.0;
+    for (size_t n = 0; n < N; ++n) {
+      double t = s + hrho0[n];
+      e += (std::fabs(s) >= std::fabs(hrho0[n])) ? (s - t) + hrho0[n] : (hrho0[n] - t) + s;
+      s = t;
+    }
+    c->rho_ave = (p->rho_ave > 0.0) ? p->rho_ave : (s + e) / (double)N;
+  }
   if (p->precision == LBM_FP32_SHIFTED) {
     // Storage shift f^eq(rho_ref, 0) (w_i rho_ref for P, rho_ref delta_i0 for
     // FE).  The default reference is the smallest initial density: the
@@ -1670,6 +1930,10 @@ lbm_status ctx_setup(const lbm_params* p, void* d_workspace, const double* d_rho
   c->lc = resolve_launch(p);
   c->kd = make_kparams<double>(p, c->rho_ref, 1, 1, c->lc.ly, 0);
   c->kf = make_kparams<float>(p, c->rho_ref, 1, 1, c->lc.ly, 0);
+  c->kd.rho_ave = c->rho_ave;
+  c->kf.rho_ave = (float)c->rho_ave;
+  c->kd.uax = c->kf.uax = (const double*)(c->ws + c->L.uax);
+  c->kd.uay = c->kf.uay = (const double*)(c->ws + c->L.uay);
   apply_launch(c);
   if (hipMemsetAsync(c->ws + c->L.flags, 0, kAlign, stream) != hipSuccess) {
     delete c;
@@ -1693,8 +1957,17 @@ lbm_status read_host(const double* d, size_t n, hipStream_t stream, std::vector<
   return LBM_OK;
 }
 
+// The collision drive acts in the steps that start at t >= ax_from_step;
+// the velocity observed at time t (Eq. 6b) uses the force of step t.
+void set_drive(lbm_ctx* c, int64_t t) {
+  const bool on = c->p.ax != 0.0 && t >= c->p.ax_from_step;
+  c->kd.ax = on ? c->p.ax : 0.0;
+  c->kf.ax = on ? (float)c->p.ax : 0.0f;
+}
+
 lbm_status observe_impl(lbm_ctx* c, int32_t cx, int32_t cy, lbm_obs* out,
                         double* d_rho, double* d_ux, double* d_uy) {
+  set_drive(c, c->step);
   if (c->p.model == LBM_MODEL_P) {
     if (c->p.eos == LBM_EOS_CS) observe_dispatch_prec<MODEL_P, EOS_CS>(c, cx, cy, d_rho, d_ux, d_uy);
     else observe_dispatch_prec<MODEL_P, EOS_VDW>(c, cx, cy, d_rho, d_ux, d_uy);
@@ -1769,7 +2042,10 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
 
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c || n < 0) return LBM_ERR_INVALID_ARG;
-  for (int64_t k = 0; k < n; ++k) step_once(c);
+  for (int64_t k = 0; k < n; ++k) {
+    set_drive(c, c->step + k);
+    step_once(c);
+  }
   c->step += n;
   if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
   return LBM_OK;
@@ -2113,6 +2389,8 @@ lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, size_t* byt
     if (st != LBM_OK) return st;
     if ((st = validate_launch(&p[i])) != LBM_OK) return st;
     if (p[i].precision != p[0].precision) return LBM_ERR_INVALID_ARG;
+    if (p[i].boundary != LBM_BOUNDARY_PERIODIC || p[i].ax != 0.0 || p[i].A != 0.0)
+      return LBM_ERR_UNSUPPORTED;
   }
   *bytes = make_batch_layout(n, p).total;
   return LBM_OK;

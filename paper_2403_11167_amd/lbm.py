@@ -20,6 +20,7 @@ OK, ERR_INVALID_ARG, ERR_EOS_DOMAIN, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ER
 MODEL_P, MODEL_FE = 0, 1
 EOS_VDW, EOS_CS = 0, 1
 FP64, FP32_SHIFTED = 0, 1
+BOUNDARY_PERIODIC, BOUNDARY_WALLS = 0, 1
 FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
 
 BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS = 0, 1, 2, 3
@@ -49,7 +50,7 @@ class LbmError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("model", ctypes.c_int32), ("eos", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("boundary", ctypes.c_int32),
                 ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("R", ctypes.c_double), ("T", ctypes.c_double),
                 ("tau", ctypes.c_double * 9),
@@ -58,7 +59,9 @@ class Params(ctypes.Structure):
                 ("A", ctypes.c_double), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
                 ("rho_ref", ctypes.c_double),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("kernel_flags", ctypes.c_uint32), ("reserved1", ctypes.c_int32)]
+                ("kernel_flags", ctypes.c_uint32), ("x_split", ctypes.c_int32),
+                ("ax", ctypes.c_double), ("rho_ave", ctypes.c_double),
+                ("ax_from_step", ctypes.c_int64)]
 
 
 class MlpNorm(ctypes.Structure):
@@ -232,18 +235,25 @@ class Config:
     tile_x: int = 0
     tile_y: int = 0
     kernel_flags: int = 0
+    walls: bool = False  # Zou-He no-slip walls on the rows y = 0 and ny - 1
+    # droplet-collision drive a(x) |rho - rho_ave| (Sec. 5.4)
+    ax: float = 0.0
+    x_split: int = 0
+    rho_ave: float = 0.0
+    ax_from_step: int = 0
 
     def c_params(self) -> Params:
         p = Params()
         p.nx, p.ny, p.model, p.eos = self.nx, self.ny, self.model, self.eos
-        p.precision, p.reserved0 = self.precision, 0
+        p.precision, p.boundary = self.precision, BOUNDARY_WALLS if self.walls else 0
         p.a, p.b, p.R, p.T = self.a, self.b, self.R, self.T
         for i, t in enumerate(self.tau):
             p.tau[i] = float(t)
         p.sigma_li, p.kappa_li, p.kappa_p = self.sigma_li, self.kappa_li, self.kappa_p
         p.kappa, p.A, p.fx, p.fy, p.rho_ref = self.kappa, self.A, self.fx, self.fy, self.rho_ref
-        p.tile_x, p.tile_y, p.kernel_flags, p.reserved1 = (self.tile_x, self.tile_y,
-                                                           self.kernel_flags, 0)
+        p.tile_x, p.tile_y, p.kernel_flags = self.tile_x, self.tile_y, self.kernel_flags
+        p.x_split, p.ax, p.rho_ave = int(self.x_split), float(self.ax), float(self.rho_ave)
+        p.ax_from_step = int(self.ax_from_step)
         return p
 
     def with_launch(self, tile_x: int, tile_y: int, kernel_flags: int) -> "Config":

@@ -53,7 +53,8 @@ def base_cfg(**kw):
     (dict(tau=[1, 1, 1, 1, 0.7, 1, 0.8, 1, 1]), lbm.ERR_INVALID_ARG),
     (dict(tau=[1, 1, 1, 1, 1, 1, 1, 1, float("nan")]), lbm.ERR_INVALID_ARG),
     (dict(model=lbm.MODEL_FE, kappa=-1.0), lbm.ERR_INVALID_ARG),
-    (dict(model=lbm.MODEL_FE, A=0.1), lbm.ERR_UNSUPPORTED),
+    (dict(model=lbm.MODEL_P, A=0.1), lbm.ERR_UNSUPPORTED),
+    (dict(model=lbm.MODEL_FE, A=0.6), lbm.ERR_INVALID_ARG),
     (dict(sigma_li=float("inf")), lbm.ERR_INVALID_ARG),
 ])
 def test_workspace_bytes_validates(kw, code):
@@ -166,3 +167,50 @@ def test_c_client_is_built_against_the_library():
     assert os.path.exists(pkg_build.DEMO)
     out = subprocess.run(["ldd", pkg_build.DEMO], capture_output=True, text=True).stdout
     assert "liblbm.so" in out and "not found" not in out.split("liblbm.so", 1)[1].splitlines()[0]
+
+
+def test_walls_validation():
+    """Walls need ny >= 3; an unknown boundary kind is rejected; batches take
+    periodic lattices only."""
+    base = lbm.Config(16, 8, lbm.MODEL_FE, lbm.EOS_CS, 0.25, 4.0, 1.0, 0.08, kappa=0.5,
+                      walls=True)
+    assert lbm.workspace_bytes(base) > 0
+    import dataclasses
+    with pytest.raises(lbm.LbmError):
+        lbm.workspace_bytes(dataclasses.replace(base, ny=2))
+    p = base.c_params()
+    p.boundary = 2
+    n = ctypes.c_size_t()
+    assert lbm.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lbm.ERR_INVALID_ARG
+    arr = (lbm.Params * 2)(base.c_params(), base.c_params())
+    assert (lbm.lib().lbm_batch_workspace_bytes(2, arr, ctypes.byref(n))
+            == lbm.ERR_UNSUPPORTED)
+    # the droplet-collision drive: single lattices only, finite, from step >= 0
+    drive = dataclasses.replace(base, walls=False, ax=5e-6, x_split=8)
+    assert lbm.workspace_bytes(drive) > 0
+    arr = (lbm.Params * 1)(drive.c_params())
+    assert lbm.lib().lbm_batch_workspace_bytes(1, arr, ctypes.byref(n)) == lbm.ERR_UNSUPPORTED
+    with pytest.raises(lbm.LbmError):
+        lbm.workspace_bytes(dataclasses.replace(drive, ax_from_step=-1))
+    with pytest.raises(lbm.LbmError):
+        lbm.workspace_bytes(dataclasses.replace(drive, ax=float("inf")))
+    # walls with a force normal to them: the closure would not conserve mass
+    p = dataclasses.replace(base, fy=1e-6).c_params()
+    assert lbm.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lbm.ERR_UNSUPPORTED
+
+
+def test_viscosity_tuning_A_validation():
+    """A != 0 (Eq. 20): free energy only, nu = c_s^2 (tau_nu - 1/2 - A) > 0
+    (Eq. 23), single lattices only; it adds two velocity planes to the
+    workspace."""
+    import dataclasses
+    fe = lbm.Config(16, 8, lbm.MODEL_FE, lbm.EOS_CS, 0.25, 4.0, 1.0, 0.08, kappa=0.5)
+    n0 = lbm.workspace_bytes(fe)
+    assert lbm.workspace_bytes(dataclasses.replace(fe, A=0.2)) >= n0 + 2 * 16 * 8 * 8
+    n = ctypes.c_size_t()
+    for bad, status in ((dataclasses.replace(fe, A=0.5), lbm.ERR_INVALID_ARG),
+                        (dataclasses.replace(fe, model=lbm.MODEL_P, A=0.1), lbm.ERR_UNSUPPORTED)):
+        p = bad.c_params()
+        assert lbm.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == status
+    arr = (lbm.Params * 1)(dataclasses.replace(fe, A=0.1).c_params())
+    assert lbm.lib().lbm_batch_workspace_bytes(1, arr, ctypes.byref(n)) == lbm.ERR_UNSUPPORTED

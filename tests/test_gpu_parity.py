@@ -62,7 +62,9 @@ def gpu_run(cfg: lbm.Config, rho0, steps, probe=(0, 0)):
 def oracle_params(cfg: lbm.Config) -> oracle.OracleParams:
     return oracle.OracleParams(cfg.nx, cfg.ny, cfg.model, cfg.eos, cfg.a, cfg.b, cfg.R, cfg.T,
                                tau=list(cfg.tau), sigma_li=cfg.sigma_li, kappa_li=cfg.kappa_li,
-                               kappa_p=cfg.kappa_p, kappa=cfg.kappa, fx=cfg.fx, fy=cfg.fy)
+                               kappa_p=cfg.kappa_p, kappa=cfg.kappa, fx=cfg.fx, fy=cfg.fy,
+                               walls=int(cfg.walls), ax=cfg.ax, x_split=cfg.x_split,
+                               rho_ave=cfg.rho_ave, ax_from_step=cfg.ax_from_step, A=cfg.A)
 
 
 def oracle_run(cfg, rho0, steps):
