@@ -162,6 +162,8 @@ def main():
                     help="skip the van der Waals Tr = 0.7 variant lines")
     ap.add_argument("--no-calibration", action="store_true",
                     help="skip the surrogate-seeded vs plain batched calibration leg")
+    ap.add_argument("--no-options", action="store_true",
+                    help="skip the general-kernel lines (walls, collision drive, A != 0)")
     ap.add_argument("--calib-train", type=int, default=2000)
     ap.add_argument("--calib-held", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -227,6 +229,31 @@ def main():
         del vr
         torch.cuda.empty_cache()
 
+    # The options of the general step kernel on the same lattice, FP64: Zou-He
+    # walls (Sec. 5.3), the droplet-collision drive (Sec. 5.4), and A != 0
+    # (Eq. 20; includes the three observation passes that form the velocity
+    # field each step).  Algorithmic bytes as for the periodic step.
+    options = None
+    if not args.no_options:
+        import dataclasses
+        ko = min(K, 500)
+        options = {"steps": ko, "precision": "fp64"}
+        cases = []
+        for mname, model in (("P", lbm.MODEL_P), ("FE", lbm.MODEL_FE)):
+            base = cfg_factory(model, lbm.FP64)
+            cases.append((f"{mname}_walls", dataclasses.replace(base, walls=True, fx=1e-7)))
+            cases.append((f"{mname}_drive", dataclasses.replace(base, ax=5e-6, x_split=args.n // 2)))
+        cases.append(("FE_A", dataclasses.replace(cfg_factory(lbm.MODEL_FE, lbm.FP64), A=0.1)))
+        for name, cfg in cases:
+            secs, obs = time_variant(cfg, rho0_dev, ko, min(W, 20))
+            ms = secs * 1e3 / ko
+            gbs = 18 * 8 * N / (ms * 1e-3) / 1e9
+            options[name] = dict(mlups=N * ko / secs / 1e6, ms_per_step=ms,
+                                 hbm_gbs_algorithmic=gbs, frac=gbs / HBM_PEAK_GBS,
+                                 flags=int(obs["flags"]), finite=bool(math.isfinite(obs["mass"])))
+            print(f"# option {name}: {ms:.4f} ms/step, {gbs / HBM_PEAK_GBS:.3f} of HBM peak",
+                  file=sys.stderr, flush=True)
+
     calib = None
     if not args.no_calibration:
         from paper_2403_11167_amd import calibration
@@ -278,6 +305,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "variants_vdw_spinodal": variants_vdw,
+        "variants_options": options,
         "calibration": calib,
         "kernel_source_hash": kernel_source_hash(),
     }

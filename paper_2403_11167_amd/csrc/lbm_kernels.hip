@@ -67,8 +67,8 @@ struct KParams {
   C ax, rho_ave;   // droplet-collision drive a(x) |rho - rho_ave| (0: off now)
   int x_split;     // a = +ax for x <= x_split, -ax beyond
   C A;             // FE: viscosity-tuning A of Eq. 20 (0: off)
-  const double* uax;  // FE with A != 0: velocity field of the current step
-  const double* uay;
+  double* uax;     // FE with A != 0: velocity field of the current step
+  double* uay;
   C rho_ref;       // sum of the storage shift s_i
   C s0, sax, sdg;  // storage shift for i = 0, axis and diagonal velocities
   // Reference terms for chemical-potential differences (shifted storage):
@@ -782,8 +782,11 @@ __device__ __forceinline__ void tile_p_pipe(const S* __restrict__ src, S* __rest
   commit_flags(fl, flags, &s_flag);
 }
 
-// Free-energy step on one tile.  GEN as for tile_p, plus the A term of
-// Eq. 20 (kp.A).
+// Free-energy step on one tile.  GEN as for tile_p; GEN = 3 adds the A term
+// of Eq. 20 (kp.A, with the velocity field in kp.uax / kp.uay).  GEN = 2 is
+// the velocity pass that the A term needs: the same pull, stencils, force
+// and wall closure, then Eq. 6b into kp.uax / kp.uay instead of a
+// collision (nothing stored to dst).
 template <int EOS, class S, class C, int BX, int NT, int CHK, int GEN = 0>
 __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict__ dst,
                                         const KParams<C>& kp, unsigned* __restrict__ flags,
@@ -907,8 +910,16 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
           gry = C(0);
           wall_fx(g0, sd, Fx);
         }
+        if constexpr (GEN == 2) {
+          const C jx = (g0[1] - g0[3]) + ((g0[5] - g0[7]) - (g0[6] - g0[8]));
+          const C jy = (g0[2] - g0[4]) + ((g0[5] - g0[7]) + (g0[6] - g0[8]));
+          const C inv = C(1) / rho;
+          kp.uax[y * nx + x] = (double)((jx + C(0.5) * Fx) * inv);
+          kp.uay[y * nx + x] = (double)((jy + C(0.5) * Fy) * inv);
+          ux = uy = C(0);
+        }
         C a_div = C(0), a_xx = C(0), a_xy = C(0);
-        if (kp.A != C(0)) {
+        if constexpr (GEN == 3) {
           C dxux, dyux, dxuy, dyuy;
           grad_u(kp.uax, nx, ny, kp.walls, x, y, dxux, dyux);
           grad_u(kp.uay, nx, ny, kp.walls, x, y, dxuy, dyuy);
@@ -917,15 +928,20 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
           a_xx = C(2.0 / 3.0) * ra * (dxux - dyuy);
           a_xy = C(1.0 / 3.0) * ra * (dxuy + dyux);
         }
-        collide<MODEL_FE, 1>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy, a_div,
-                             a_xx, a_xy);
+        if constexpr (GEN == 1)
+          collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
+        if constexpr (GEN == 3)
+          collide<MODEL_FE, 1>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy, a_div,
+                               a_xx, a_xy);
       } else {
         collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
       }
       chk_node<CHK>(ck, y * nx + x, ux, uy, dmax);
-      const int off = y * kp.rowpitch + c0;
+      if constexpr (GEN != 2) {
+        const int off = y * kp.rowpitch + c0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)g0[i]);
+        for (int i = 0; i < 9; ++i) st<NT>(&dst[off + 64 * i], (S)g0[i]);
+      }
 #pragma unroll
       for (int i = 0; i < 9; ++i) { g0[i] = g1[i]; g1[i] = g2[i]; }
       d0 = d1;
@@ -1757,34 +1773,30 @@ int grid1d(size_t N) {
 // S = grad u + grad u^T needs the neighbours' velocities.
 template <int MODEL, int EOS, class S, class C, int BX>
 void launch_step_gen(lbm_ctx* c, const KParams<C>& kp) {
+  // the FE kernels take the periodic kernel's register target (a tighter
+  // cap spills); GEN = 3 carries the A term, GEN = 1 the other options
+  constexpr int WG = (MODEL == MODEL_FE) ? wpe_target<MODEL_FE, S>() : 0;
+  const bool with_a = MODEL == MODEL_FE && c->p.A != 0.0;
   if (c->lc.auto_ly) {
     if constexpr (MODEL == MODEL_P) tune_ly(c, k_step_p<EOS, S, C, BX, 1, 0, 1>, BX);
-    else tune_ly(c, k_step_fe<EOS, S, C, BX, 1, 0, 1>, BX);
+    else if (with_a) tune_ly(c, k_step_fe<EOS, S, C, BX, 1, WG, 3>, BX);
+    else tune_ly(c, k_step_fe<EOS, S, C, BX, 1, WG, 1>, BX);
   }
   const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
   S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
   unsigned* flags = (unsigned*)(c->ws + c->L.flags);
-  if constexpr (MODEL == MODEL_FE) {
-    if (c->p.A != 0.0) {
-      double* rho_w = (double*)(c->ws + c->L.rho_w);
-      double* aux_w = (double*)(c->ws + c->L.aux_w);
-      size_t N = (size_t)c->p.nx * c->p.ny;
-      hipLaunchKernelGGL((k_obs_rho<MODEL_FE, EOS, S>), dim3(grid1d(N)), dim3(256), 0, c->stream,
-                         src, c->kd, rho_w, aux_w, flags);
-      hipLaunchKernelGGL((k_obs_mu<EOS>), dim3(grid1d(N)), dim3(256), 0, c->stream, c->kd,
-                         (const double*)rho_w, aux_w);
-      hipLaunchKernelGGL((k_obs_u<MODEL_FE, S, kObsThreads>), dim3(c->L.obs_blocks),
-                         dim3(kObsThreads), 0, c->stream, src, c->kd, (const double*)rho_w,
-                         (const double*)aux_w, (double*)nullptr, (double*)nullptr,
-                         (double*)nullptr, (double*)(c->ws + c->L.uax),
-                         (double*)(c->ws + c->L.uay), 0, (ObsPartial*)(c->ws + c->L.part));
-    }
-  }
   dim3 grid(c->nstrips * c->nseg), block(BX);
+  if constexpr (MODEL == MODEL_FE) {
+    if (c->p.A != 0.0)  // the step's velocity field first (GEN = 2 pass)
+      hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, 1, WG, 2>), grid, block, 0, c->stream, src, dst,
+                         kp, flags);
+  }
   if constexpr (MODEL == MODEL_P)
     hipLaunchKernelGGL((k_step_p<EOS, S, C, BX, 1, 0, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
+  else if (with_a)
+    hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, 1, WG, 3>), grid, block, 0, c->stream, src, dst, kp, flags);
   else
-    hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, 1, 0, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
+    hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, 1, WG, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
   c->cur ^= 1;
 }
 
@@ -1932,8 +1944,8 @@ lbm_status ctx_setup(const lbm_params* p, void* d_workspace, const double* d_rho
   c->kf = make_kparams<float>(p, c->rho_ref, 1, 1, c->lc.ly, 0);
   c->kd.rho_ave = c->rho_ave;
   c->kf.rho_ave = (float)c->rho_ave;
-  c->kd.uax = c->kf.uax = (const double*)(c->ws + c->L.uax);
-  c->kd.uay = c->kf.uay = (const double*)(c->ws + c->L.uay);
+  c->kd.uax = c->kf.uax = (double*)(c->ws + c->L.uax);
+  c->kd.uay = c->kf.uay = (double*)(c->ws + c->L.uay);
   apply_launch(c);
   if (hipMemsetAsync(c->ws + c->L.flags, 0, kAlign, stream) != hipSuccess) {
     delete c;
