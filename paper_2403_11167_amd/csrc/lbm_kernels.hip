@@ -437,29 +437,30 @@ __device__ __forceinline__ int wall_side(int y, int ny) {
 // symmetric under c -> -c.
 template <class C>
 __device__ __forceinline__ void wall_fill(C g[9], int side, C fy) {
+  // both walls' values from the original populations, then selected by
+  // value: branches on `side` writing different slots would be merged into
+  // indexed stores, which put g[] in scratch memory
   const C t = C(0.5) * (g[1] - g[3]);
   const C h = C(-0.25) * fy;  // jy / 2
-  if (side > 0) {
-    g[2] = g[4];
-    g[5] = g[7] - t + h;
-    g[6] = g[8] + t + h;
-  } else {
-    g[4] = g[2];
-    g[7] = g[5] + t - h;
-    g[8] = g[6] - t - h;
-  }
+  const bool b = side > 0;
+  const C n2 = g[4], n5 = g[7] - t + h, n6 = g[8] + t + h;  // bottom wall
+  const C s4 = g[2], s7 = g[5] + t - h, s8 = g[6] - t - h;  // top wall
+  g[2] = b ? n2 : g[2];
+  g[5] = b ? n5 : g[5];
+  g[6] = b ? n6 : g[6];
+  g[4] = b ? g[4] : s4;
+  g[7] = b ? g[7] : s7;
+  g[8] = b ? g[8] : s8;
 }
 
 template <class C>
 __device__ __forceinline__ void wall_fx(C g[9], int side, C Fx) {
   const C q = C(0.25) * Fx;  // -jx / 2
-  if (side > 0) {
-    g[5] -= q;
-    g[6] += q;
-  } else {
-    g[7] += q;
-    g[8] -= q;
-  }
+  const bool b = side > 0;
+  g[5] = b ? g[5] - q : g[5];
+  g[6] = b ? g[6] + q : g[6];
+  g[7] = b ? g[7] : g[7] + q;
+  g[8] = b ? g[8] : g[8] - q;
 }
 
 // ---- per-tile step bodies -------------------------------------------------
