@@ -1741,24 +1741,31 @@ void tune_ly(lbm_ctx* c, K kernel, int bx) {
 
 template <int MODEL, int EOS, class S, class C, int BX, int NT, int WPE>
 void launch_step_w(lbm_ctx* c, const KParams<C>& kp) {
+  // compile-time model branches: each model instantiates only its own kernels
   if (c->lc.auto_ly) {
-    if (MODEL == MODEL_P && c->lc.pipe) tune_ly(c, k_step_p_pipe<EOS, S, C, BX, NT, WPE>, BX);
-    else if (MODEL == MODEL_P) tune_ly(c, k_step_p<EOS, S, C, BX, NT, WPE>, BX);
-    else if (c->lc.pipe) tune_ly(c, k_step_fe_pipe<EOS, S, C, BX, NT, WPE>, BX);
-    else tune_ly(c, k_step_fe<EOS, S, C, BX, NT, WPE>, BX);
+    if constexpr (MODEL == MODEL_P) {
+      if (c->lc.pipe) tune_ly(c, k_step_p_pipe<EOS, S, C, BX, NT, WPE>, BX);
+      else tune_ly(c, k_step_p<EOS, S, C, BX, NT, WPE>, BX);
+    } else {
+      if (c->lc.pipe) tune_ly(c, k_step_fe_pipe<EOS, S, C, BX, NT, WPE>, BX);
+      else tune_ly(c, k_step_fe<EOS, S, C, BX, NT, WPE>, BX);
+    }
   }
   const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
   S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
   unsigned* flags = (unsigned*)(c->ws + c->L.flags);
   dim3 grid(c->nstrips * c->nseg), block(BX);
-  if (MODEL == MODEL_P && c->lc.pipe)
-    hipLaunchKernelGGL((k_step_p_pipe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
-  else if (MODEL == MODEL_P)
-    hipLaunchKernelGGL((k_step_p<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
-  else if (c->lc.pipe)
-    hipLaunchKernelGGL((k_step_fe_pipe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
-  else
-    hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+  if constexpr (MODEL == MODEL_P) {
+    if (c->lc.pipe)
+      hipLaunchKernelGGL((k_step_p_pipe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+    else
+      hipLaunchKernelGGL((k_step_p<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+  } else {
+    if (c->lc.pipe)
+      hipLaunchKernelGGL((k_step_fe_pipe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+    else
+      hipLaunchKernelGGL((k_step_fe<EOS, S, C, BX, NT, WPE>), grid, block, 0, c->stream, src, dst, kp, flags);
+  }
   c->cur ^= 1;
 }
 
