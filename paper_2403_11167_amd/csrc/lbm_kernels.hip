@@ -597,6 +597,11 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
   for (int r = 0; r < 2; ++r) {
     const int y = seen(y0 - 1 + r);
     const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
+    // halo loads first, so that they are in flight with the interior ones:
+    // waiting for the interior loads then covers both (one round trip, not
+    // two, for the wavefront that holds the halo lanes)
+    C h[9];
+    if (hl) pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
     if (active) {
       C g[9];
       pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
@@ -611,10 +616,8 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
       }
     }
     if (hl) {
-      C g[9];
-      pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, g);
-      close(y, g);
-      C rho = kp.rho_ref + sum9(g);
+      close(y, h);
+      C rho = kp.rho_ref + sum9(h);
       psi_s[r][hj] = psi_of<EOS>(rho, kp, fl);
     }
   }
@@ -626,6 +629,8 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
       const int yn = seen(y + 1);
       const int r0 = rowoff(yn), rm = rowoff(yn - 1), rp = rowoff(yn + 1);
       C* row = psi_s[(k + 2) & 3];
+      C h[9];
+      if (hl) pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);  // halo first
       if (active) {
         pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, gn);
         close(yn, gn);
@@ -635,10 +640,8 @@ __device__ __forceinline__ void tile_p(const S* __restrict__ src, S* __restrict_
         row[t + 1] = psi_of<EOS>(rho, kp, fl);
       }
       if (hl) {
-        C g[9];
-        pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, g);
-        close(yn, g);
-        C rho = kp.rho_ref + sum9(g);
+        close(yn, h);
+        C rho = kp.rho_ref + sum9(h);
         row[hj] = psi_of<EOS>(rho, kp, fl);
       }
     }
@@ -838,6 +841,9 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
     }
     const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
     C* row = rho_s[slot & 7];
+    // halo loads first, in flight with the interior ones (one round trip)
+    C h[9];
+    if (hr) pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
     if (active) {
       pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
       if (GEN != 0 && sd) wall_fill(g, sd, kp.fy);
@@ -846,8 +852,6 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
       row[t + 2] = dr;
     }
     if (hr) {
-      C h[9];
-      pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
       if (GEN != 0 && sd) wall_fill(h, sd, kp.fy);
       row[hj] = sum9(h);
     }
