@@ -74,7 +74,10 @@ struct KParams {
   // Reference terms for chemical-potential differences (shifted storage):
   C inv_rho_ref;   // 1 / rho_ref
   C om_ref;        // 1 - b rho_ref (vdW) or 1 - b rho_ref / 4 (CS)
+  C inv_om_ref;    // 1 / om_ref
+  C inv_om_ref3;   // 1 / om_ref^3
 };
+
 
 template <class C>
 __device__ __forceinline__ C d_sqrt(C v) {
@@ -85,6 +88,17 @@ __device__ __forceinline__ C d_log(C v) {
   if constexpr (sizeof(C) == 4) return logf(v); else return log(v);
 }
 
+// Reciprocal in the compute type.  FP32 (shifted storage) takes the
+// hardware reciprocal (1 ulp) instead of the correctly rounded division
+// sequence: the FP32 step is bound by its vector ALU, and an ulp here is
+// below the storage rounding its error bounds already carry.  FP64 keeps
+// the correctly rounded division.
+template <class C>
+__device__ __forceinline__ C recip(C v) {
+  if constexpr (sizeof(C) == 4) return __builtin_amdgcn_rcpf(v);
+  else return C(1) / v;
+}
+
 // ---- equations of state ---------------------------------------------------
 // Carnahan-Starling (Eq. 28) and van der Waals pressure.
 template <int EOS, class C>
@@ -93,9 +107,9 @@ __device__ __forceinline__ C eos_p(C rho, const KParams<C>& kp) {
     C e = kp.b * rho * C(0.25);
     C om = C(1) - e;
     C num = C(1) + e * (C(1) + e * (C(1) - e));
-    return rho * kp.RT * num / (om * om * om) - kp.a * rho * rho;
+    return rho * kp.RT * num * recip(om * om * om) - kp.a * rho * rho;
   } else {
-    return rho * kp.RT / (C(1) - kp.b * rho) - kp.a * rho * rho;
+    return rho * kp.RT * recip(C(1) - kp.b * rho) - kp.a * rho * rho;
   }
 }
 
@@ -138,15 +152,16 @@ __device__ __forceinline__ C mu_dev(C d, const KParams<C>& kp) {
   } else {
     C lr = kp.RT * d_log1p(d * kp.inv_rho_ref);
     if constexpr (EOS == EOS_CS) {
+      // both rational terms over the common denominator u^3 u_r^3:
+      // [2 (u_r^2 + u u_r + u^2) + (u + u_r) u u_r] / (u^3 u_r^3)
       C u = kp.om_ref - kp.b * d * C(0.25), ur = kp.om_ref;
-      C u2 = u * u, ur2 = ur * ur;
-      C dg = kp.b * d * C(0.25) *
-             (C(2) * (ur2 + u * ur + u2) / (u2 * u * ur2 * ur) + (u + ur) / (u2 * ur2));
+      C num = C(2) * (ur * ur + u * ur + u * u) + (u + ur) * u * ur;
+      C dg = kp.b * d * C(0.25) * num * recip(u * u * u) * kp.inv_om_ref3;
       return kp.RT * dg + lr - C(2) * kp.a * d;
     } else {
       C om = kp.om_ref - kp.b * d;  // 1 - b rho
-      return lr - kp.RT * d_log1p(-kp.b * d / kp.om_ref) +
-             kp.RT * kp.b * d / (om * kp.om_ref) - C(2) * kp.a * d;
+      return lr - kp.RT * d_log1p(-kp.b * d * kp.inv_om_ref) +
+             kp.RT * kp.b * d * recip(om) * kp.inv_om_ref - C(2) * kp.a * d;
     }
   }
 }
@@ -289,7 +304,7 @@ __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
   // FE: t0 = d_x rho, t1 = d_y rho.
   C jx = (g[1] - g[3]) + ((g[5] - g[7]) - (g[6] - g[8]));
   C jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
-  C inv = C(1) / rho;
+  C inv = recip(rho);
   C ux = (jx + C(0.5) * Fx) * inv;  // Eq. 6b
   C uy = (jy + C(0.5) * Fy) * inv;
   ux_out = ux;
@@ -1601,7 +1616,10 @@ KParams<C> make_kparams(const lbm_params* p, double rho_ref, int nstrips,
   k.sdg = (C)sdg;
   k.rho_ref = (C)rho_ref;
   k.inv_rho_ref = (C)(rho_ref > 0 ? 1.0 / rho_ref : 0.0);
-  k.om_ref = (C)(p->eos == LBM_EOS_CS ? 1.0 - 0.25 * p->b * rho_ref : 1.0 - p->b * rho_ref);
+  const double om_ref = p->eos == LBM_EOS_CS ? 1.0 - 0.25 * p->b * rho_ref : 1.0 - p->b * rho_ref;
+  k.om_ref = (C)om_ref;
+  k.inv_om_ref = (C)(1.0 / om_ref);
+  k.inv_om_ref3 = (C)(1.0 / (om_ref * om_ref * om_ref));
   return k;
 }
 
