@@ -75,19 +75,21 @@ def test_walls_fp32_shifted_match_oracle(model):
 
 
 @pytest.mark.parametrize("model", [lbm.MODEL_FE, lbm.MODEL_P])
-@pytest.mark.parametrize("Tr", [0.8, 0.7])
+@pytest.mark.parametrize("Tr", [0.8, 0.7, 0.6])
 def test_channel_flow_steady_state(model, Tr):
     """Sec. 5.3 at its geometry: 101 x 50, walls on rows 0 and 49, vapour
     below and liquid above, F_x = 1e-6 (Tr 0.8) or 5e-7 (Tr 0.7), run 20000
-    steps to a steady state (later change < 1e-6 of the peak).  The flow is
+    steps to a steady state (later change < 1e-6 of the peak; at Tr 0.6 the
+    FE flow still drifts by ~1e-3 per 20000 steps).  The flow is
     uniform in x, so the oracle runs the same problem on 3 columns: every
     node of the GPU field must match it (1e-10 on rho, 1e-8 of the peak on
     u).  Against App. F Eq. 89 (with the lattice's own density profile) the
     measured deviation is a second-order discretisation error of the
     method (it falls 4x when the interface width doubles, pinned on the
-    oracle): 3.6 % (FE) and 0.74 % (P) at Tr 0.8, 10.2 % and 1.5 % at 0.7;
-    the bars sit just above."""
-    fx = 1e-6 if Tr == 0.8 else 5e-7
+    oracle): 3.6 % (FE) and 0.74 % (P) at Tr 0.8, 10.2 % and 1.5 % at 0.7,
+    15 % and 1.6 % at 0.6 (F_x = 2e-7), the FE error growing as the paper
+    reports for its Fig. 6; the bars sit just above."""
+    fx = {0.8: 1e-6, 0.7: 5e-7, 0.6: 2e-7}[Tr]
     cfg, rho0 = channel_cfg(model, Tr, fx=fx)
     steps = 20000
     obs, rho, ux, uy = gpu_run(cfg, rho0, steps)
@@ -101,5 +103,23 @@ def test_channel_flow_steady_state(model, Tr):
     ud = th.plates_diffuse(fx, np.arange(ny), rho[:, 0] * (cfg.tau[7] - 0.5) / 3)
     dev = np.abs(ux[:, 0] - ud).max() / ud.max()
     bar = {(lbm.MODEL_FE, 0.8): 0.04, (lbm.MODEL_P, 0.8): 0.01,
-           (lbm.MODEL_FE, 0.7): 0.11, (lbm.MODEL_P, 0.7): 0.02}[(model, Tr)]
+           (lbm.MODEL_FE, 0.7): 0.11, (lbm.MODEL_P, 0.7): 0.02,
+           (lbm.MODEL_FE, 0.6): 0.17, (lbm.MODEL_P, 0.6): 0.02}[(model, Tr)]
     assert dev < bar, dev
+
+
+def test_channel_at_tr_0_5_only_pseudopotential_stable():
+    """Sec. 5.3: at Tr = 0.5 (F_x = 1e-7) only the pseudopotential run stays
+    stable.  On the oracle the FE channel raises its non-finite / EOS-domain
+    flags by step 3300, with or without the force (the FE model's low-Tr
+    limit), while P reaches a steady flow within 1.1 % of App. F Eq. 89."""
+    flags = {}
+    for model in (lbm.MODEL_FE, lbm.MODEL_P):
+        cfg, rho0 = channel_cfg(model, 0.5, fx=1e-7)
+        obs, rho, ux, _ = gpu_run(cfg, rho0, 20000)
+        flags[model] = obs["flags"]
+        if model == lbm.MODEL_P:
+            assert obs["flags"] == 0 and np.isfinite(ux).all()
+            ud = th.plates_diffuse(1e-7, np.arange(cfg.ny), rho[:, 0] * 0.5 / 3)
+            assert np.abs(ux[:, 0] - ud).max() / ud.max() < 0.015
+    assert flags[lbm.MODEL_FE] & (lbm.FLAG_NONFINITE | lbm.FLAG_EOS_DOMAIN)
