@@ -108,3 +108,38 @@ def test_collision_merge_times():
     assert steps[lbm.MODEL_P] < steps[lbm.MODEL_FE]
     tstar = {m: t * np.sqrt(AX / 50.0) for m, t in steps.items()}
     assert 1.7 < tstar[lbm.MODEL_P] < 2.1 and 1.8 < tstar[lbm.MODEL_FE] < 2.2, tstar
+
+
+@pytest.mark.parametrize("Tr,model,stable,steps", [
+    (0.7, lbm.MODEL_FE, False, 9000), (0.7, lbm.MODEL_P, True, 9000),
+    (0.6, lbm.MODEL_P, True, 9000), (0.5, lbm.MODEL_P, False, 4000)])
+def test_collision_stability_over_temperature(Tr, model, stable, steps):
+    """Sec. 5.4 end: at Tr = 0.7 the FE collision turns unstable during the
+    merging, while P stays stable at 0.7 and 0.6 and not at 0.5 (the
+    oracle: FE 0.7 merges at t = 6100 and raises its flags by 7200; P 0.5 by
+    2500; P 0.7 and 0.6 merge at 5600 and 5400 and run clean to 12000).
+    Same set-up as Fig. 8, P parameters matched to the FE model at each Tr."""
+    import torch
+    a = 0.25
+    T = cs_T(a, Tr)
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    tau = [1.0] * 9
+    if model == lbm.MODEL_FE:
+        tau[1] = 0.75
+        kw = dict(kappa=0.5)
+    else:
+        m = th.match_p_to_fe(th.CS, a, 4.0, 1.0, T, 0.5)
+        tau[4] = tau[6] = 1 / 1.99
+        kw = dict(sigma_li=m["sigma_li"], kappa_p=m["kappa_p"], kappa_li=m["kappa_li"])
+    cfg = lbm.Config(200, 100, model, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tau, ax=AX, x_split=SPLIT,
+                     ax_from_step=T_ON, **kw)
+    rho0 = inputs.droplets(200, 100, rl, rv, 25.0, [(50.0, 50.0), (150.0, 50.0)])
+    sim = lbm.Simulation(cfg, torch.from_numpy(rho0).to(torch_dev()))
+    sim.step(steps)
+    obs = sim.observe(100, 50)
+    sim.close()
+    if stable:
+        assert obs["flags"] == 0
+        assert obs["rho_in"] >= 0.5 * (rl + rv)  # merged: the midpoint is liquid
+    else:
+        assert obs["flags"] & (lbm.FLAG_NONFINITE | lbm.FLAG_EOS_DOMAIN)
