@@ -252,7 +252,8 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
        within rtol_rho, sigma within rtol_sigma, W within rtol_w) is done
        with the measured labels; every other tuple keeps running from its
        current state to the plain method's convergence criterion (the
-       fallback).
+       fallback), within the plain run's step budget: max_steps per
+       lattice, the verification steps included.
     Returns (labels, info) like run_calibration, info with the number of
     tuples accepted after verification and the prediction array."""
     import time
@@ -280,8 +281,10 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
     states = batch.state()[0]
     fb = set(fallback)
     resume = [i for i, (k, _) in enumerate(meta) if k in fb and states[i] == lbm.BATCH_MAXSTEPS]
+    # the same per-lattice budget as the plain run: max_steps in total,
+    # verification steps included
     for i in resume:
-        batch.set_limit(i, 2 ** 62)
+        batch.set_limit(i, max_steps)
     steps2 = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps) if resume else 0
     if fallback:
         measure(batch, cfgs, meta, len(tuples), which=fallback, labels=labels)

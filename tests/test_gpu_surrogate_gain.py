@@ -13,13 +13,20 @@ from paper_2403_11167_amd import inputs, lbm
 pytestmark = pytest.mark.gpu
 
 
-def test_surrogate_replaces_calibration_runs():
-    import torch
+@pytest.fixture(scope="module")
+def trained():
+    """The surrogate trained on 600 sampled tuples (flat 64 x 8, droplet 96^2)."""
     x, y, info = cal.training_set(600, 15, size=(64, 8, 96), max_steps=60000)
-    assert len(x) > 250
     sur = lbm.Surrogate(inputs.mlp_initial_params(0))
     sur.set_target_scaling(y)
     losses = sur.fit(x, y, epochs=400, batch=128, lr=3e-3, seed=1, lr_final=1e-4)
+    return x, sur, losses
+
+
+def test_surrogate_replaces_calibration_runs(trained):
+    import torch
+    x, sur, losses = trained
+    assert len(x) > 250
     assert losses[-1] < 0.02 * losses[0]
     # held-out tuples, calibrated by the plain method on the training geometry
     tup = cal.sample_tuples(48, 16)
@@ -41,3 +48,25 @@ def test_surrogate_replaces_calibration_runs():
     assert np.median(rel[:, 2]) < 0.03
     # the prediction replaces runs that take seconds
     assert infer < 0.05 * plain["seconds"], (infer, plain["seconds"])
+
+
+def test_seeded_calibration_keeps_the_plain_budget(trained):
+    """Seeded calibration: every tuple is either accepted after verification
+    or finished by the plain method; no lattice runs beyond the plain run's
+    per-lattice step budget (the verification steps count against it); and
+    where both runs converge they reach the same labels."""
+    _, sur, _ = trained
+    n, budget = 32, 20000
+    tup = cal.sample_tuples(n, 17)
+    sizes = [(64, 8, 96)] * n
+    lab_p, inf_p = cal.run_calibration(tup, sizes, max_steps=budget)
+    lab_s, inf_s = cal.run_seeded_calibration(tup, sizes, sur, max_steps=budget, crossings=8.0)
+    assert inf_s["accepted"] + inf_s["fallback"] == n
+    assert max(inf_p["steps_per_problem"]) <= budget
+    assert max(inf_s["steps_per_problem"]) <= budget, inf_s["steps_per_problem"]
+    rel, m = cal.compare(lab_p, lab_s)
+    assert m.sum() >= 10
+    assert np.mean(rel["rho_l"] < cal.TOLERANCES["rho_l"]) >= 0.9
+    assert np.mean(rel["W"] < cal.TOLERANCES["W"]) >= 0.9
+    assert np.median(rel["rho_v"]) < cal.TOLERANCES["rho_v"]
+    assert np.median(rel["sigma"]) < cal.TOLERANCES["sigma"]
