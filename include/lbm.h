@@ -219,6 +219,7 @@ typedef struct lbm_batch lbm_batch;
 #define LBM_BATCH_CONVERGED 1
 #define LBM_BATCH_UNSTABLE 2
 #define LBM_BATCH_MAXSTEPS 3
+#define LBM_BATCH_DROPPED 4 /* retired because its partner became unstable */
 
 lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, size_t* bytes);
 
@@ -243,6 +244,16 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol,
  * limit becomes active again and continues from its current state at the
  * next lbm_batch_run().  Host-only; no device work. */
 lbm_status lbm_batch_set_limit(lbm_batch* b, int32_t i, int64_t max_steps);
+
+/* Problems i and j form one unit, such as the flat and the droplet lattice
+ * of one calibration tuple, whose results are only of use together: when
+ * either becomes LBM_BATCH_UNSTABLE, the other, if still active, retires
+ * with LBM_BATCH_DROPPED before the next step (it keeps its state and step
+ * count, and a later lbm_batch_set_limit() does not resume it).  A pair
+ * may be set again; i == j, an index out of range, or a problem that
+ * already has a different partner gives LBM_ERR_INVALID_ARG.  Host-only; no
+ * device work. */
+lbm_status lbm_batch_set_partner(lbm_batch* b, int32_t i, int32_t j);
 
 /* Per-problem state (LBM_BATCH_*), steps taken, last measured max |du| and
  * sticky flags; each pointer may be NULL, else points to n elements. */

@@ -174,6 +174,18 @@ def build_problems(tuples, sizes, precision, guesses=None):
     return cfgs, rho0s, meta
 
 
+def pair_units(batch, meta):
+    """The flat and the droplet lattice of each tuple form one unit: a tuple
+    whose lattice goes unstable has no labels, so its other lattice retires
+    (lbm_batch_set_partner) instead of running on to the step limit."""
+    first = {}
+    for i, (k, _) in enumerate(meta):
+        if k in first:
+            batch.set_partner(first[k], i)
+        else:
+            first[k] = i
+
+
 def run_calibration(tuples, sizes, precision=lbm.FP32_SHIFTED, guesses=None,
                     check_every=200, du_tol=1e-9, max_steps=200000):
     """Run the flat + droplet pair of every tuple to equilibrium in one batch.
@@ -188,6 +200,7 @@ def run_calibration(tuples, sizes, precision=lbm.FP32_SHIFTED, guesses=None,
     cfgs, rho0s, meta = build_problems(tuples, sizes, precision, guesses)
     t0 = time.perf_counter()
     batch = lbm.Batch(cfgs, [torch.from_numpy(r).to(dev) for r in rho0s])
+    pair_units(batch, meta)
     steps = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps)
     labels = measure(batch, cfgs, meta, len(tuples))
     seconds = time.perf_counter() - t0
@@ -264,6 +277,7 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
     pred = surrogate.predict(features(tuples))
     cfgs, rho0s, meta = build_problems(tuples, sizes, precision, seeded_guesses(pred))
     batch = lbm.Batch(cfgs, [torch.from_numpy(r).to(dev) for r in rho0s])
+    pair_units(batch, meta)
     for i, c in enumerate(cfgs):
         v = crossings * max(c.nx, c.ny) / CS_LATTICE
         batch.set_limit(i, int(math.ceil(v / check_every)) * check_every)

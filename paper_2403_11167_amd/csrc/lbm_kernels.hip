@@ -2213,6 +2213,7 @@ struct BatchInst {
   int checks;
   uint32_t flags;
   int64_t limit;    // retire with LBM_BATCH_MAXSTEPS once steps >= limit
+  int partner;      // the other problem of its unit, or -1
 };
 
 struct GroupKey {
@@ -2477,7 +2478,7 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
   for (int i = 0; i < n && st == LBM_OK; ++i) {
     BatchInst& I = b->inst[i];
     I = BatchInst{nullptr, B.chk_off[i], LBM_BATCH_ACTIVE, 0, INFINITY, INFINITY, 0, 0, 0u,
-                  INT64_MAX};
+                  INT64_MAX, -1};
     st = read_host(d_rho0[i], (size_t)p[i].nx * p[i].ny, stream, h);
     if (st == LBM_OK) st = ctx_setup(&p[i], b->ws + B.inst_off[i], d_rho0[i], h, stream, &I.ctx);
   }
@@ -2532,6 +2533,13 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
     for (auto& I : b->inst) {
       if (I.state == LBM_BATCH_ACTIVE && I.steps >= I.limit) {
         I.state = LBM_BATCH_MAXSTEPS;
+        b->tables_valid = false;
+      }
+      // a unit whose other problem became unstable (at the last check) has
+      // no use for this one: it retires before any further step
+      if (I.state == LBM_BATCH_ACTIVE && I.partner >= 0 &&
+          b->inst[I.partner].state == LBM_BATCH_UNSTABLE) {
+        I.state = LBM_BATCH_DROPPED;
         b->tables_valid = false;
       }
       any |= (I.state == LBM_BATCH_ACTIVE);
@@ -2591,7 +2599,14 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
       I.ctx->have_prev = 0;
     }
     bool any = false;
-    for (auto& I : b->inst) any |= (I.state == LBM_BATCH_ACTIVE);
+    for (auto& I : b->inst) {
+      if (I.state == LBM_BATCH_ACTIVE && I.partner >= 0 &&
+          b->inst[I.partner].state == LBM_BATCH_UNSTABLE) {
+        I.state = LBM_BATCH_DROPPED;  // the partner failed at the last check
+        b->tables_valid = false;
+      }
+      any |= (I.state == LBM_BATCH_ACTIVE);
+    }
     if (any && done >= max_steps)
       for (auto& I : b->inst)
         if (I.state == LBM_BATCH_ACTIVE) I.state = LBM_BATCH_MAXSTEPS;
@@ -2616,6 +2631,17 @@ lbm_status lbm_batch_set_limit(lbm_batch* b, int32_t i, int64_t max_steps) {
     I.best_du = INFINITY;
     b->tables_valid = false;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_partner(lbm_batch* b, int32_t i, int32_t j) {
+  if (!b || i < 0 || i >= b->n || j < 0 || j >= b->n || i == j) return LBM_ERR_INVALID_ARG;
+  BatchInst& I = b->inst[i];
+  BatchInst& J = b->inst[j];
+  if ((I.partner >= 0 && I.partner != j) || (J.partner >= 0 && J.partner != i))
+    return LBM_ERR_INVALID_ARG;
+  I.partner = j;
+  J.partner = i;
   return LBM_OK;
 }
 

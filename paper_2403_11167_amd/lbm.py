@@ -23,7 +23,7 @@ FP64, FP32_SHIFTED = 0, 1
 BOUNDARY_PERIODIC, BOUNDARY_WALLS = 0, 1
 FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
 
-BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS = 0, 1, 2, 3
+BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS, BATCH_DROPPED = 0, 1, 2, 3, 4
 KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE = 0x80000000, 1, 2, 4
 
 EXPORTED_SYMBOLS = [
@@ -32,7 +32,7 @@ EXPORTED_SYMBOLS = [
     "lbm_eos_eval", "lbm_eos_critical", "lbm_maxwell", "lbm_sigma_li_theory", "lbm_fe_planar_theory",
     "lbm_match_p_to_fe",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_state",
-    "lbm_batch_observe", "lbm_batch_destroy", "lbm_batch_set_limit",
+    "lbm_batch_observe", "lbm_batch_destroy", "lbm_batch_set_limit", "lbm_batch_set_partner",
     "lbm_mlp_forward", "lbm_mlp_workspace_bytes", "lbm_mlp_grad", "lbm_mlp_adam",
     "lbm_mlp_train_step",
 ]
@@ -139,6 +139,7 @@ def lib():
                                         ctypes.POINTER(Obs), vp, vp, vp]
         L.lbm_batch_destroy.argtypes = [vp]
         L.lbm_batch_set_limit.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
+        L.lbm_batch_set_partner.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         NP = ctypes.POINTER(MlpNorm)
         i32, f32 = ctypes.c_int32, ctypes.c_float
         L.lbm_mlp_forward.argtypes = [vp, NP, vp, i32, vp, i32, vp]
@@ -391,6 +392,10 @@ class Batch:
     def set_limit(self, i: int, max_steps: int):
         """Step limit of problem i (see lbm_batch_set_limit)."""
         _check(lib().lbm_batch_set_limit(self._h, int(i), int(max_steps)), "lbm_batch_set_limit")
+
+    def set_partner(self, i: int, j: int):
+        """Problems i and j form one unit (see lbm_batch_set_partner)."""
+        _check(lib().lbm_batch_set_partner(self._h, int(i), int(j)), "lbm_batch_set_partner")
 
     def state(self):
         """(state, steps, du, flags) lists."""

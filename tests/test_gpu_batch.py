@@ -136,6 +136,49 @@ def test_batch_convergence_and_retirement():
     b.close()
 
 
+def test_partner_of_an_unstable_problem_retires_with_it():
+    """Two problems paired as one unit: when the unstable free-energy van
+    der Waals spinodal retires as unstable, its partner retires as dropped
+    at the same step count and keeps its state (equal to the oracle's); a
+    later step limit does not resume it; an unpaired copy of the partner
+    runs on past that step."""
+    a = 0.5
+    T = cs_T(a, 0.7)
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    Tv = 0.7 * 4 / 7
+    rlv, rvv, _ = th.maxwell(th.VDW, 9 / 49, 2 / 21, 1.0, Tv)
+    cfgs = [lbm.Config(100, 4, 1, lbm.EOS_CS, a, 4.0, 1.0, T, kappa=0.5),
+            lbm.Config(64, 64, 1, lbm.EOS_VDW, 9 / 49, 2 / 21, 1.0, Tv, kappa=0.5),
+            lbm.Config(100, 4, 1, lbm.EOS_CS, a, 4.0, 1.0, T, kappa=0.5)]
+    r0s = [inputs.planar_slab(100, 4, rl, rv),
+           inputs.spinodal(64, 64, 0.5 * (rlv + rvv), 0.01, seed=3),
+           inputs.planar_slab(100, 4, rl, rv)]
+    b = lbm.Batch(cfgs, [to_dev(r) for r in r0s])
+    for i, j in ((0, 0), (0, 3), (-1, 1)):
+        with pytest.raises(lbm.LbmError):
+            b.set_partner(i, j)
+    b.set_partner(0, 1)
+    b.set_partner(1, 0)  # the same pair again
+    with pytest.raises(lbm.LbmError):
+        b.set_partner(0, 2)  # 0 already has a partner
+    steps = 30000
+    b.run(check_every=200, du_tol=0.0, max_steps=steps)
+    st, nsteps, _, fl = b.state()
+    assert st[1] == lbm.BATCH_UNSTABLE and fl[1] & (lbm.FLAG_NONFINITE | lbm.FLAG_EOS_DOMAIN)
+    assert nsteps[1] < steps
+    assert st[0] == lbm.BATCH_DROPPED and nsteps[0] == nsteps[1], (st, nsteps)
+    # the copy evolved identically, so it was active at that check too
+    assert st[2] in (lbm.BATCH_CONVERGED, lbm.BATCH_MAXSTEPS) and nsteps[2] > nsteps[0]
+    _, (rho, _, _) = b.observe(0, fields=True)
+    rref, _ = oracle_rho(cfgs[0], r0s[0], nsteps[0])
+    assert rel(rho.cpu().numpy(), rref) < FP64_RTOL
+    b.set_limit(0, 10 ** 9)
+    b.run(check_every=200, du_tol=0.0, max_steps=1000)
+    st2, nsteps2, _, _ = b.state()
+    assert st2[0] == lbm.BATCH_DROPPED and nsteps2[0] == nsteps[0]
+    b.close()
+
+
 @pytest.mark.parametrize("model", [0, 1])
 def test_autotuned_launch_keeps_parity(model):
     a = 0.25
