@@ -250,6 +250,18 @@ def measure(batch, cfgs, meta, ntuples, which=None, labels=None,
 CS_LATTICE = 1.0 / math.sqrt(3.0)
 
 
+def lattice_labels(batch, cfgs, i, kind):
+    """Labels one lattice measures: (rho_l, rho_v, W) of a flat interface or
+    (sigma, drop_contrast) of a droplet, from the batch's current state."""
+    if kind == "flat":
+        _, (rho, _, _) = batch.observe(i, fields=True)
+        rl, rv, W = flat_labels(rho.cpu().numpy())
+        return dict(rho_l=rl, rho_v=rv, W=W)
+    L = cfgs[i].nx
+    obs = batch.observe(i, L // 2, L // 2)
+    return dict(sigma=droplet_sigma(obs), drop_contrast=float(obs["rho_in"] - obs["rho_out"]))
+
+
 def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
                            check_every=200, du_tol=1e-9, max_steps=200000,
                            crossings=8.0, rtol_rho=0.01, rtol_sigma=0.03, rtol_w=0.05):
@@ -261,14 +273,19 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
     2. Verification: each lattice runs at most `crossings` sound crossings
        of its box (max(nx, ny) / c_s steps each), retiring earlier if it
        converges.
-    3. A tuple whose measured labels agree with the prediction (densities
-       within rtol_rho, sigma within rtol_sigma, W within rtol_w) is done
-       with the measured labels; every other tuple keeps running from its
-       current state to the plain method's convergence criterion (the
-       fallback), within the plain run's step budget: max_steps per
-       lattice, the verification steps included.
-    Returns (labels, info) like run_calibration, info with the number of
-    tuples accepted after verification and the prediction array."""
+    3. Each lattice is judged on the labels it measures: a flat lattice
+       whose densities agree with the prediction within rtol_rho and width
+       within rtol_w, or a droplet whose sigma agrees within rtol_sigma (and
+       that is still a droplet), is done with its measured labels, as is a
+       lattice that met the convergence rule; every other lattice keeps
+       running from its current state to the plain method's convergence
+       rule (the fallback), within the plain run's step budget: max_steps
+       per lattice, the verification steps included.
+    A tuple is valid when both its lattices are done (accepted or
+    converged) and its droplet is still a droplet.  Returns (labels, info)
+    like run_calibration; info counts the tuples with both lattices
+    accepted after verification ("accepted"), the accepted lattices, and
+    holds the prediction array."""
     import time
 
     import torch
@@ -283,34 +300,58 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
         v = crossings * max(c.nx, c.ny) / CS_LATTICE
         batch.set_limit(i, int(math.ceil(v / check_every)) * check_every)
     steps = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps)
-    labels = measure(batch, cfgs, meta, len(tuples),
-                     accept=(lbm.BATCH_CONVERGED, lbm.BATCH_MAXSTEPS))
-    accepted, fallback = [], []
-    for k, lab in enumerate(labels):
-        p = pred[k]
-        agree = (lab["ok"] and abs(lab["rho_l"] / p[0] - 1) <= rtol_rho
-                 and abs(lab["rho_v"] / p[1] - 1) <= rtol_rho
-                 and abs(lab["sigma"] / p[2] - 1) <= rtol_sigma
-                 and abs(lab["W"] / p[3] - 1) <= rtol_w)
-        (accepted if agree else fallback).append(k)
     states = batch.state()[0]
-    fb = set(fallback)
-    resume = [i for i, (k, _) in enumerate(meta) if k in fb and states[i] == lbm.BATCH_MAXSTEPS]
+    lat = [None] * len(cfgs)
+    accepted = [False] * len(cfgs)
+    resume = []
+    for i, (k, kind) in enumerate(meta):
+        if states[i] == lbm.BATCH_CONVERGED:
+            lat[i] = lattice_labels(batch, cfgs, i, kind)
+            continue
+        if states[i] != lbm.BATCH_MAXSTEPS:
+            continue  # unstable, or dropped with its partner
+        m = lattice_labels(batch, cfgs, i, kind)
+        p = pred[k]
+        if kind == "flat":
+            agree = (abs(m["rho_l"] / p[0] - 1) <= rtol_rho and abs(m["rho_v"] / p[1] - 1) <= rtol_rho
+                     and abs(m["W"] / p[3] - 1) <= rtol_w)
+        else:
+            agree = (m["drop_contrast"] > 0.5 * (p[0] - p[1])
+                     and abs(m["sigma"] / p[2] - 1) <= rtol_sigma)
+        if agree:
+            lat[i], accepted[i] = m, True
+        else:
+            resume.append(i)
     # the same per-lattice budget as the plain run: max_steps in total,
     # verification steps included
     for i in resume:
         batch.set_limit(i, max_steps)
     steps2 = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps) if resume else 0
-    if fallback:
-        measure(batch, cfgs, meta, len(tuples), which=fallback, labels=labels)
-    seconds = time.perf_counter() - t0
     states, nsteps, du, flags = batch.state()
+    for i in resume:
+        if states[i] == lbm.BATCH_CONVERGED:
+            lat[i] = lattice_labels(batch, cfgs, i, meta[i][1])
+    labels = [dict(rho_l=math.nan, rho_v=math.nan, W=math.nan, sigma=math.nan, ok=True)
+              for _ in tuples]
+    both = [0] * len(tuples)
+    for i, (k, kind) in enumerate(meta):
+        if lat[i] is None:
+            labels[k]["ok"] = False
+        else:
+            labels[k].update(lat[i])
+        both[k] += accepted[i]
+    for lab in labels:
+        if not (lab.get("drop_contrast", 0.0) > 0.5 * (lab["rho_l"] - lab["rho_v"])):
+            lab["ok"] = False
+    seconds = time.perf_counter() - t0
     batch.close()
     units = sum(1 for lab in labels if lab["ok"])
+    n_acc = sum(1 for v in both if v == 2)
     info = dict(seconds=seconds, steps=steps + steps2, states=states, steps_per_problem=nsteps,
                 problems=len(cfgs), converged_units=units,
                 units_per_second=units / seconds if seconds > 0 else math.nan,
-                accepted=len(accepted), fallback=len(fallback), prediction=pred)
+                accepted=n_acc, accepted_lattices=int(sum(accepted)),
+                fallback=len(tuples) - n_acc, prediction=pred)
     return labels, info
 
 
@@ -442,6 +483,7 @@ def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_
         seeded=dict(seconds=inf_s["seconds"], tuples_converged=inf_s["converged_units"],
                     tuples_per_s=inf_s["units_per_second"], lockstep_steps=inf_s["steps"],
                     accepted_after_verification=inf_s["accepted"],
+                    lattices_accepted_after_verification=inf_s["accepted_lattices"],
                     fallback=inf_s["fallback"], verification_crossings=crossings),
         speedup=inf_p["seconds"] / inf_s["seconds"],
         surrogate_only=dict(seconds=infer_s, tuples=n_held,
