@@ -262,6 +262,19 @@ def lattice_labels(batch, cfgs, i, kind):
     return dict(sigma=droplet_sigma(obs), drop_contrast=float(obs["rho_in"] - obs["rho_out"]))
 
 
+def lattice_agrees(kind, m, p, rtol_rho=0.01, rtol_sigma=0.03, rtol_w=0.05) -> bool:
+    """Verification of one lattice against the prediction p = (rho_l, rho_v,
+    sigma, W): a flat lattice's measured densities within rtol_rho and width
+    within rtol_w; a droplet's sigma within rtol_sigma, with the droplet
+    still a droplet (core-to-far-field contrast above half the predicted
+    density gap).  A NaN measurement never agrees."""
+    if kind == "flat":
+        return bool(abs(m["rho_l"] / p[0] - 1) <= rtol_rho and abs(m["rho_v"] / p[1] - 1) <= rtol_rho
+                    and abs(m["W"] / p[3] - 1) <= rtol_w)
+    return bool(m["drop_contrast"] > 0.5 * (p[0] - p[1])
+                and abs(m["sigma"] / p[2] - 1) <= rtol_sigma)
+
+
 def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
                            check_every=200, du_tol=1e-9, max_steps=200000,
                            crossings=8.0, rtol_rho=0.01, rtol_sigma=0.03, rtol_w=0.05):
@@ -311,14 +324,7 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
         if states[i] != lbm.BATCH_MAXSTEPS:
             continue  # unstable, or dropped with its partner
         m = lattice_labels(batch, cfgs, i, kind)
-        p = pred[k]
-        if kind == "flat":
-            agree = (abs(m["rho_l"] / p[0] - 1) <= rtol_rho and abs(m["rho_v"] / p[1] - 1) <= rtol_rho
-                     and abs(m["W"] / p[3] - 1) <= rtol_w)
-        else:
-            agree = (m["drop_contrast"] > 0.5 * (p[0] - p[1])
-                     and abs(m["sigma"] / p[2] - 1) <= rtol_sigma)
-        if agree:
+        if lattice_agrees(kind, m, pred[k], rtol_rho, rtol_sigma, rtol_w):
             lat[i], accepted[i] = m, True
         else:
             resume.append(i)

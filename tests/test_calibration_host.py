@@ -1,0 +1,39 @@
+"""Host logic of the calibration driver (no device work): the seed of each
+model and the per-lattice verification rule."""
+import math
+
+import numpy as np
+
+from oracle import theory as th
+from paper_2403_11167_amd import calibration as cal
+from paper_2403_11167_amd import lbm
+
+
+def test_free_energy_seed_takes_maxwell_densities():
+    """A free-energy tuple is seeded with the Maxwell densities (the model
+    meets the Maxwell rule, Sec. 5.1) and the predicted width and sigma; a
+    pseudopotential tuple with all four predictions."""
+    tuples = [cal.Tuple4(lbm.MODEL_FE, 0.8, 4.0, 1.0), cal.Tuple4(lbm.MODEL_P, 0.8, 4.0, 1.0)]
+    pred = np.array([[0.31, 0.012, 0.02, 5.5], [0.32, 0.011, 0.03, 4.5]])
+    g = cal.seeded_guesses(pred, tuples=tuples)
+    T = 0.8 * cal.critical_T()
+    rl, rv, _ = th.maxwell(th.CS, cal.A, cal.B, cal.RGAS, T)
+    assert math.isclose(g[0][0], rl, rel_tol=1e-9) and math.isclose(g[0][1], rv, rel_tol=1e-9)
+    assert g[0][2:] == (5.5, 0.02)
+    assert g[1] == (0.32, 0.011, 4.5, 0.03)
+    # without tuples every seed is the prediction
+    assert cal.seeded_guesses(pred)[0] == (0.31, 0.012, 5.5, 0.02)
+
+
+def test_lattice_verification_rule():
+    p = (0.30, 0.010, 0.020, 5.0)
+    flat = dict(rho_l=0.3025, rho_v=0.01009, W=5.2)
+    assert cal.lattice_agrees("flat", flat, p)
+    assert not cal.lattice_agrees("flat", dict(flat, rho_v=0.0102), p)  # 2 %
+    assert not cal.lattice_agrees("flat", dict(flat, W=5.3), p)         # 6 %
+    assert not cal.lattice_agrees("flat", dict(flat, rho_l=math.nan), p)
+    drop = dict(sigma=0.0205, drop_contrast=0.25)
+    assert cal.lattice_agrees("droplet", drop, p)
+    assert not cal.lattice_agrees("droplet", dict(drop, sigma=0.0207), p)   # 3.5 %
+    # a droplet that dissolved measures no surface tension
+    assert not cal.lattice_agrees("droplet", dict(drop, drop_contrast=0.1), p)
