@@ -37,3 +37,19 @@ def test_lattice_verification_rule():
     assert not cal.lattice_agrees("droplet", dict(drop, sigma=0.0207), p)   # 3.5 %
     # a droplet that dissolved measures no surface tension
     assert not cal.lattice_agrees("droplet", dict(drop, drop_contrast=0.1), p)
+
+
+def test_each_tuple_is_one_unit():
+    """pair_units pairs the flat and the droplet lattice of each tuple, and
+    nothing else."""
+    class Rec:
+        def __init__(self):
+            self.pairs = []
+
+        def set_partner(self, i, j):
+            self.pairs.append((i, j))
+
+    meta = [(0, "flat"), (0, "droplet"), (1, "flat"), (1, "droplet"), (2, "flat"), (2, "droplet")]
+    r = Rec()
+    cal.pair_units(r, meta)
+    assert r.pairs == [(0, 1), (2, 3), (4, 5)]
