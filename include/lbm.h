@@ -89,7 +89,10 @@ typedef enum { LBM_BOUNDARY_PERIODIC = 0, LBM_BOUNDARY_WALLS = 1 } lbm_boundary;
 
 /* Problem statement (Sec. 2, Sec. 5).  Plain data; copied by lbm_init(). */
 typedef struct {
-  int32_t nx, ny;       /* lattice, 1 <= nx, ny; nx * ny < 2^31            */
+  int32_t nx, ny;       /* lattice, 1 <= nx, ny, and
+                            ny * 576 * ceil(nx / 64) < 2^31 (population
+                            offsets are 32-bit): about 2.4e8 nodes, e.g.
+                            15360 x 15360; larger is LBM_ERR_INVALID_ARG  */
   int32_t model;        /* lbm_model                                        */
   int32_t eos;          /* lbm_eos                                          */
   int32_t precision;    /* lbm_precision                                    */

@@ -44,6 +44,8 @@ def base_cfg(**kw):
     (dict(nx=0), lbm.ERR_INVALID_ARG),
     (dict(ny=-3), lbm.ERR_INVALID_ARG),
     (dict(nx=70000, ny=70000), lbm.ERR_INVALID_ARG),
+    # nx * ny < 2^31, but ny * 576 * ceil(nx / 64) (the population offsets) is not
+    (dict(nx=16384, ny=16384), lbm.ERR_INVALID_ARG),
     (dict(model=2), lbm.ERR_INVALID_ARG),
     (dict(eos=5), lbm.ERR_INVALID_ARG),
     (dict(precision=3), lbm.ERR_INVALID_ARG),
@@ -61,6 +63,11 @@ def test_workspace_bytes_validates(kw, code):
     with pytest.raises(lbm.LbmError) as e:
         lbm.workspace_bytes(base_cfg(**kw))
     assert e.value.status == code
+
+
+def test_largest_lattice_with_32_bit_offsets_is_accepted():
+    # 15360 x 15360: 15360 * 576 * 240 = 2.12e9 < 2^31
+    assert lbm.workspace_bytes(base_cfg(nx=15360, ny=15360)) > 2 * 9 * 8 * 15360 * 15360
 
 
 def test_workspace_size_scales_with_precision():
