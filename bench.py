@@ -298,7 +298,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "lattice": f"{args.n}x{args.n}",
-                   "lbm_models": ["pseudopotential (P)", "well-balanced free energy (FE)"],
+                   "methods": ["pseudopotential (P)", "well-balanced free energy (FE)"],
                    "step": "one update of each model's lattice",
                    "parallelism": "single GPU"},
         "roofline": roofline,
