@@ -16,14 +16,7 @@ from paper_2403_11167_amd import build as pkg_build
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("model", [lbm.MODEL_P, lbm.MODEL_FE])
-def test_c_client_matches_oracle(model):
-    assert os.path.exists(pkg_build.DEMO), "build the library first (it builds the C client)"
-    nx, ny, steps = 130, 98, 150
-    res = subprocess.run([pkg_build.DEMO, str(model), str(nx), str(ny), str(steps)],
-                         capture_output=True, text=True, timeout=120)
-    assert res.returncode == 0, res.stderr
-    got = json.loads(res.stdout.strip().splitlines()[-1])
+def check_against_oracle(got, model, nx, ny, steps):
     a, b, R = 0.25, 4.0, 1.0
     T = 0.8 * th.critical(th.CS, a, b, R)[0]
     rl, rv, _ = th.maxwell(th.CS, a, b, R, T)
@@ -48,3 +41,28 @@ def test_c_client_matches_oracle(model):
     assert math.isclose(got["rho_out"], ref["rho_out"], rel_tol=1e-10)
     assert math.isclose(got["dp"], ref["dp"], rel_tol=1e-7)
     assert math.isclose(got["r_equimolar"], ref["r_equimolar"], rel_tol=1e-9)
+
+
+@pytest.mark.parametrize("model", [lbm.MODEL_P, lbm.MODEL_FE])
+def test_c_client_matches_oracle(model):
+    assert os.path.exists(pkg_build.DEMO), "build the library first (it builds the C client)"
+    nx, ny, steps = 130, 98, 150
+    res = subprocess.run([pkg_build.DEMO, str(model), str(nx), str(ny), str(steps)],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stderr
+    got = json.loads(res.stdout.strip().splitlines()[-1])
+    check_against_oracle(got, model, nx, ny, steps)
+
+
+def test_c_client_batch_matches_oracle():
+    """The batch entry points from plain C: both models' droplets in one
+    paired batch, each equal to its own oracle run."""
+    assert os.path.exists(pkg_build.DEMO), "build the library first (it builds the C client)"
+    nx, ny, steps = 130, 98, 150
+    res = subprocess.run([pkg_build.DEMO, "batch", str(nx), str(ny), str(steps)],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stderr
+    lines = [json.loads(l) for l in res.stdout.strip().splitlines() if l.startswith("{")]
+    assert [g["model"] for g in lines] == [lbm.MODEL_P, lbm.MODEL_FE]
+    for got in lines:
+        check_against_oracle(got, got["model"], nx, ny, steps)
