@@ -171,7 +171,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for {args.gpus}); "
               "the lattice would shard by 2-D domain decomposition, not implemented here.",
               file=sys.stderr)
         raise SystemExit(2)

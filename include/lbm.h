@@ -59,7 +59,7 @@ typedef enum {
   LBM_OK = 0,
   LBM_ERR_INVALID_ARG = -1,  /* bad pointer, size or parameter value        */
   LBM_ERR_EOS_DOMAIN = -2,   /* equation of state undefined for an input    */
-  LBM_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement */
+  LBM_ERR_UNSUPPORTED = -3,  /* valid request the library does not implement */
   LBM_ERR_WORKSPACE = -4,    /* workspace missing, too small or misaligned  */
   LBM_ERR_HIP = -5,          /* a HIP runtime call failed                   */
   LBM_ERR_NO_CONVERGENCE = -6 /* a host-side solver did not converge        */
