@@ -526,9 +526,11 @@ static unsigned fields_and_forces(const orc_params *p, const double *f,
     int side = wall_side(p, (int)(n / (size_t)nx));
     if (side) wall_close(fn, side, 0.0, 0.0);
     for (int i = 0; i < 9; ++i) s += fn[i];
-    /* a wall node also carries sum f c_y = jy(rho), which adds jy to its
-     * density (it does not depend on jx) */
-    if (side) s += wall_jy(p);
+    /* a wall node also carries sum f c_y = jy: closing with jy moves the
+     * two diagonal unknowns (c_y = side) by jy in sum f c_y, so the density
+     * changes by side * jy (+jy on the bottom wall, -jy on the top one); it
+     * does not depend on jx */
+    if (side) s += side * wall_jy(p);
     w->rho[n] = s;
     if (!isfinite(s)) flags |= ORC_FLAG_NONFINITE;
     if (!eos_domain_ok(p, s)) flags |= ORC_FLAG_EOS_DOMAIN;
