@@ -375,14 +375,30 @@ def test_fe_planar_vapor_error_independent_of_tau_v():
     assert abs(e[0] - e[1]) < 2e-3 * e[0]
 
 
-@pytest.mark.parametrize("kp", [1.0, 0.4])
-def test_p_planar_satisfies_appendix_e_relation(kp):
-    """App. E Eq. 76: with tau_e = tau_nu, the per-node quantity
+_P_PLANAR = {}
+
+
+@pytest.mark.parametrize("kp,tau_env,tau_z", [(1.0, 1.0, 1.0), (0.4, 1.0, 1.0),
+                                              (1.0, 0.8, 1.3), (0.4, 0.8, 1.3),
+                                              (1.0, 1.3, 0.7), (0.4, 1.3, 0.7)])
+def test_p_planar_satisfies_appendix_e_relation(kp, tau_env, tau_z):
+    """App. E Eq. 76: with tau_e = tau_nu the per-node quantity
     p_EOS + (G/4) kP psi (psi_{n+1} - 2 psi_n + psi_{n-1}) +
     2 G^2 kP sigma ((psi_{n+1} - psi_{n-1})/2)^2 is uniform at steady state.
     The oracle's planar steady state must satisfy it and agree with an
     independent Newton solve.  (With C_2 printed without G the relation
-    fails and the kP = 0.4 vapour error would be ~77 % instead of ~9.6 %.)"""
+    fails and the kP = 0.4 vapour error would be ~77 % instead of ~9.6 %.)
+
+    The relation holds for any common tau_e = tau_nu: in Eq. 71 the forcing
+    factor (1 - lambda_e/2) / (tau_e - 1/2) of the Eq. 32 consistency term
+    equals lambda_e, and the Eq. 13 source carries lambda_e and lambda_nu,
+    so dividing by lambda leaves no tau.  The zeta row cancels from Eq. 71
+    (Eq. 69 + 2 x Eq. 70) and from the sum of Eq. 72, so tau_zeta (here
+    different from tau_e) must not matter either.  Hence the cases at
+    tau_e = tau_nu = 0.8 and 1.3 with tau_zeta = 1.3 and 0.7: a 1/tau where
+    the paper has tau, a tau_zeta where it has tau_e, or a (1 - lambda/2)
+    factor taken from the wrong row breaks the relation, and the steady
+    profile must equal the tau = 1 one."""
     a, b, R, T = cs_params(0.5, 0.65)
     rl, rv, p0 = th.maxwell(th.CS, a, b, R, T)
     eps, sig = th.epsilon_li(th.CS, a, b, R, T)
@@ -390,10 +406,12 @@ def test_p_planar_satisfies_appendix_e_relation(kp):
     rho0 = inputs.planar_slab(L, 1, rl, rv, width=5.0)
     tau = [1.0] * 9
     tau[4] = tau[6] = 1 / 1.99
+    tau[1] = tau[7] = tau[8] = tau_env
+    tau[2] = tau_z
     p = oracle.OracleParams(L, 1, oracle.MODEL_P, oracle.EOS_CS, a, b, R, T, tau=tau,
                             sigma_li=sig, kappa_p=kp, kappa_li=0.0)
     s = oracle.Simulation(p, rho0)
-    s.step(50000)
+    s.step(60000)
     rho = s.fields()[0][0]
     E = th.planar_p_invariant(th.CS, a, b, R, T, kp, sig, rho)
     assert E.max() - E.min() < 1e-13
@@ -405,6 +423,82 @@ def test_p_planar_satisfies_appendix_e_relation(kp):
     err = 100 * abs(rho.min() - rv) / rv
     assert err < (3.0 if kp == 1.0 else 12.0)
     assert s.flags == 0
+    if tau_env == 1.0:
+        _P_PLANAR[kp] = rho
+    elif kp in _P_PLANAR:
+        assert np.abs(rho - _P_PLANAR[kp]).max() < 1e-9
+
+
+def test_p_planar_resting_populations_satisfy_appendix_e_67_68():
+    """App. E Eq. 67-68 (written out as Eq. 69-70): in a planar state the
+    populations f_0 and f_2 do not stream along the profile, so once the
+    state repeats, the collision's changes to them add up to zero.  With
+    M^-1 of Eq. 49 (rows 0 and 2) the change of f_0 is
+    (1/9) (C_zeta - C_e) and that of f_2 is
+    -(1/36) C_e - (1/18) C_zeta - (1/4) C_nu, where each row's change is
+    C_k = -lam_k m_k^neq + (1 - lam_k/2) mF_k + mC_k with mF of Eq. 32 and mC
+    of Eq. 13 (Eq. 66 in 1-D).  Unlike Eq. 76 these involve the zeta row, so
+    they pin its consistency and source terms as well.  This state settles
+    into a period-2 odd-even oscillation of u_x (~4e-7) on a steady density,
+    so the sums are taken over two consecutive steps, which must vanish to
+    rounding while each step's change is ~1e-8.  Every tau differs
+    (tau_e 0.8, tau_zeta 1.3, tau_q 1/1.99, tau_nu 1.1) and kappa^P = 0.6,
+    kappa^Li = 0.3 make Q non-zero.  The moments come from the populations
+    through their velocity polynomials, psi, F, K = G^2 S^2 and Q from the
+    density field through Eq. 10, 11 and 30 in their 1-D forms."""
+    a, b, R, T = cs_params(0.5, 0.7)
+    rl, rv, _ = th.maxwell(th.CS, a, b, R, T)
+    _, sig = th.epsilon_li(th.CS, a, b, R, T)
+    kp, kli = 0.6, 0.3
+    te, tz, tn = 0.8, 1.3, 1.1
+    tau = [1.0, te, tz, 1.0, 1 / 1.99, 1.0, 1 / 1.99, tn, tn]
+    L = 100
+    p = oracle.OracleParams(L, 1, oracle.MODEL_P, oracle.EOS_CS, a, b, R, T, tau=tau,
+                            sigma_li=sig, kappa_p=kp, kappa_li=kli)
+    s = oracle.Simulation(p, inputs.planar_slab(L, 1, rl, rv, width=5.0))
+    s.step(60000)
+    G = -1.0
+    le, lz, ln = 1 / te, 1 / tz, 1 / tn
+    c2 = (CX ** 2 + CY ** 2)[:, None]
+    d0, d2 = [], []
+    for _ in range(2):
+        rho, ux, uy = s.fields()
+        assert np.abs(uy).max() < 1e-13 and s.flags == 0
+        rho, u = rho[0], ux[0]
+        f = s.f[:, 0, :]
+        ps = th.psi(th.CS, rho, a, b, R, T)
+        pp, pm = np.roll(ps, -1), np.roll(ps, 1)
+        Sx = 0.5 * (pp - pm)                       # Eq. 10 sum along x
+        F = -G * ps * Sx
+        K = G * G * Sx ** 2
+        C1, C2 = 5 / 6 * (kp - 1), 0.5 * G * (1 - kp)
+        Q = np.zeros((2, 2, L))                    # Eq. 30, neighbours along x only
+        for i in range(1, 9):
+            d = np.roll(ps, -CX[i]) - ps
+            om = 1 / 3 if CX[i] ** 2 + CY[i] ** 2 == 1 else 1 / 12
+            c = (CX[i], CY[i])
+            for al in range(2):
+                for be in range(2):
+                    dl = 1.0 if al == be else 0.0
+                    Q[al, be] += om * (C1 * G * dl + C2 * (c[al] * c[be] - dl / 3)
+                                       + kli * 0.5 * G * c[al] * c[be]) * d
+        Q *= ps
+        Qs, Qd = Q[0, 0] + Q[1, 1], Q[0, 0] - Q[1, 1]
+        # non-equilibrium moments against the Eq. 4 / Eq. 66 equilibrium
+        ne = (f * (-4 + 3 * c2)).sum(0) - rho * (-2 + 3 * u * u)
+        nz = (f * (4 - 10.5 * c2 + 4.5 * c2 ** 2)).sum(0) - rho * (1 - 3 * u * u)
+        nn = (f * (CX ** 2 - CY ** 2)[:, None]).sum(0) - rho * u * u
+        ks = 12 * kp * sig * K
+        Ce = -le * ne + (1 - le / 2) * (6 * u * F + ks / (te - 0.5)) + 1.5 * le * Qs
+        Cz = -lz * nz + (1 - lz / 2) * (-6 * u * F - ks / (tz - 0.5)) - 1.5 * lz * Qs
+        Cn = -ln * nn + (1 - ln / 2) * (2 * u * F) - ln * Qd
+        d0.append((Cz - Ce) / 9)
+        d2.append(-Ce / 36 - Cz / 18 - Cn / 4)
+        s.step(1)
+    scale = max(np.abs(d0[0]).max(), np.abs(d2[0]).max())
+    assert scale > 1e-9
+    assert np.abs(d0[0] + d0[1]).max() < 1e-6 * scale
+    assert np.abs(d2[0] + d2[1]).max() < 1e-6 * scale
 
 
 def test_kappa_p_changes_width_as_sqrt():
