@@ -51,7 +51,8 @@ class _Params(ctypes.Structure):
                 ("fx", ctypes.c_double), ("fy", ctypes.c_double),
                 ("walls", ctypes.c_int32), ("x_split", ctypes.c_int32),
                 ("ax", ctypes.c_double), ("rho_ave", ctypes.c_double),
-                ("A", ctypes.c_double)]
+                ("A", ctypes.c_double), ("g", ctypes.c_double),
+                ("rho0_g", ctypes.c_double), ("y_g", ctypes.c_double)]
 
 
 @dataclass
@@ -63,7 +64,9 @@ class OracleParams:
     a(x) |rho - rho_ave| with a = +ax for x <= x_split and -ax beyond, in the
     steps that start at t >= ax_from_step; rho_ave <= 0 takes the mean of
     the initial density.  Free energy only: A is the viscosity-tuning
-    parameter of Eq. 20."""
+    parameter of Eq. 20, and g, rho0_g, y_g its gravity (walls only):
+    p_g = rho0_g g (y - y_g) in Eq. 20, buoyancy -(rho - rho0_g) g in y,
+    d_y p_g in Eq. 21; g > 0 pulls toward -y."""
     nx: int
     ny: int
     model: int
@@ -85,6 +88,9 @@ class OracleParams:
     rho_ave: float = 0.0
     ax_from_step: int = 0
     A: float = 0.0
+    g: float = 0.0
+    rho0_g: float = 0.0
+    y_g: float = 0.0
 
     def _c(self) -> _Params:
         p = _Params()
@@ -97,6 +103,7 @@ class OracleParams:
         p.walls = int(self.walls)
         p.x_split, p.ax, p.rho_ave = int(self.x_split), float(self.ax), float(self.rho_ave)
         p.A = float(self.A)
+        p.g, p.rho0_g, p.y_g = float(self.g), float(self.rho0_g), float(self.y_g)
         return p
 
 

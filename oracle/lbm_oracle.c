@@ -9,9 +9,9 @@
  *            forcing scaled by kappa^P (Eq. 32), source term (Eq. 13) with
  *            the width-controlling Q tensor (Eq. 30-31);
  *   model 1  improved well-balanced free energy (IWB-FE-LBM): equilibrium
- *            (Eq. 20) and forcing (Eq. 21) with A = 0 and p_g = 0, chemical
- *            potential mu = mu_b - kappa lap(rho) (Sec. 2.2) and the
- *            9-point stencils of Eq. 24.
+ *            (Eq. 20) and forcing (Eq. 21), chemical potential
+ *            mu = mu_b - kappa lap(rho) (Sec. 2.2) and the 9-point stencils
+ *            of Eq. 24; A (R9) and gravity (R10) are optional.
  *
  * TEST INFRASTRUCTURE ONLY.  This file exists so that the GPU path can be
  * checked against something slow and obviously correct.  Only the test
@@ -61,8 +61,17 @@
  *       wall the velocity is reflected with its sign flipped, so it vanishes
  *       on the wall row as the closure imposes.  The initial equilibrium
  *       takes S from the initial velocity the same way (zero for a fluid at
- *       rest).  Gravity (p_g, F_g) is written into the equilibrium and
- *       forcing functions but not used by the step.
+ *       rest).
+ *   R10 Free energy with gravity (Sec. 2.2, optional, walls only): p_g =
+ *       rho_0 g (y - y_g) enters the equilibrium of Eq. 20 at every node
+ *       (y the node's row, y_g the row where p_g = 0), the buoyancy force
+ *       F_g = -(rho - rho_0) g in y joins the total force F, and d_y p_g =
+ *       rho_0 g enters Eq. 21.  With g > 0 gravity pulls toward -y: the
+ *       momentum gains -d_y p_g + F_g = -rho g.  p_g is not periodic, hence
+ *       walls.  On a wall row the normal force is f_y + F_g (R7), which
+ *       depends on the wall density; the closure then fixes that density
+ *       through a linear equation, solved in closed form.  The initial
+ *       equilibrium carries p_g too.
  */
 #include <math.h>
 #include <stdint.h>
@@ -94,6 +103,7 @@ typedef struct {
   int32_t x_split;      /* drive (R8): +ax for x <= x_split, -ax beyond */
   double ax, rho_ave;   /* drive (R8); ax = 0: off */
   double A;             /* free energy: viscosity-tuning A of Eq. 20 (R9) */
+  double g, rho0_g, y_g; /* free energy: gravity (R10); g = 0: off */
 } orc_params;
 
 /* ---- lattice (Eq. 2 and the weights stated under Eq. 4) ------------------ */
@@ -416,6 +426,11 @@ void orc_forcing_fe_full(double ux, double uy, double Fx, double Fy, double gx,
   forcing_well_balanced(ux, uy, Fx, Fy, gx, gy, dpgy, Fi);
 }
 
+/* p_g of Eq. 20 on row y (R10); 0 without gravity. */
+static double pg_row(const orc_params *p, int y) {
+  return p->rho0_g * p->g * ((double)y - p->y_g);
+}
+
 /* Population layout: f[i * N + y * nx + x], N = nx * ny, holding f_i(x, t)
  * after streaming (the left-hand side of Eq. 1 at the previous step). */
 
@@ -439,7 +454,7 @@ void orc_init(const orc_params *p, const double *rho0, const double *ux0,
       double dn[4] = {0.0, 0.0, 0.0, 0.0};
       if (with_a)
         for (int k = 0; k < 4; ++k) dn[k] = du[k][n];
-      feq_well_balanced(rho0[n], ux, uy, 0.0, p->A, dn, feq);
+      feq_well_balanced(rho0[n], ux, uy, pg_row(p, (int)(n / (size_t)nx)), p->A, dn, feq);
     } else {
       feq_standard(rho0[n], ux, uy, feq);
     }
@@ -485,9 +500,20 @@ static void wall_close(double *fn, int side, double jx, double jy) {
   fn[d[1]] = (CX[d[0]] * by - CY[d[0]] * bx) / det;
 }
 
-/* Normal momentum sum f c_y = -F_y/2 of a wall node, with F_y = fy its
- * normal body force: the interaction force vanishes there (R7). */
-static double wall_jy(const orc_params *p) { return -0.5 * p->fy; }
+/* Normal force of a wall node of density rho: the body force fy plus the
+ * buoyancy of R10; the interaction force vanishes there (R7).  The node
+ * carries sum f c_y = -F_y/2. */
+static double wall_fy(const orc_params *p, double rho) {
+  return p->fy - (rho - p->rho0_g) * p->g;
+}
+
+/* Density of a wall node on `side` whose populations closed with zero
+ * normal momentum sum to s: closing with j_y = -F_y/2 moves the two
+ * diagonal unknowns, whose c_y is `side`, by j_y in sum f c_y, so the
+ * density is rho = s + side j_y(rho), linear in rho with F_y of wall_fy. */
+static double wall_rho(const orc_params *p, int side, double s) {
+  return (s - side * 0.5 * (p->fy + p->g * p->rho0_g)) / (1.0 - side * 0.5 * p->g);
+}
 
 /* Per-step field work shared by the step and by the field export: density,
  * and the model's force ingredients.  Arrays are length N. */
@@ -526,11 +552,10 @@ static unsigned fields_and_forces(const orc_params *p, const double *f,
     int side = wall_side(p, (int)(n / (size_t)nx));
     if (side) wall_close(fn, side, 0.0, 0.0);
     for (int i = 0; i < 9; ++i) s += fn[i];
-    /* a wall node also carries sum f c_y = jy: closing with jy moves the
-     * two diagonal unknowns (c_y = side) by jy in sum f c_y, so the density
-     * changes by side * jy (+jy on the bottom wall, -jy on the top one); it
-     * does not depend on jx */
-    if (side) s += side * wall_jy(p);
+    /* a wall node also carries sum f c_y = j_y, which moves its density by
+     * side * j_y (+j_y on the bottom wall, -j_y on the top one); jx does not
+     * change it */
+    if (side) s = wall_rho(p, side, s);
     w->rho[n] = s;
     if (!isfinite(s)) flags |= ORC_FLAG_NONFINITE;
     if (!eos_domain_ok(p, s)) flags |= ORC_FLAG_EOS_DOMAIN;
@@ -573,7 +598,8 @@ static void node_force(const orc_params *p, const orc_work *w, size_t n,
     *Fy = fyi + p->fy;
   } else {
     *Fx = -w->rho[n] * w->gmx[n] + body_fx(p, w, n); /* F = -rho grad(mu) */
-    *Fy = -w->rho[n] * w->gmy[n] + p->fy;
+    /* plus the buoyancy F_g = -(rho - rho_0) g (R10) */
+    *Fy = -w->rho[n] * w->gmy[n] + p->fy - (w->rho[n] - p->rho0_g) * p->g;
     *K = 0.0;
   }
 }
@@ -587,7 +613,7 @@ static void velocity_field(const orc_params *p, const double *f, orc_work *w) {
     node_force(p, w, n, &Fx, &Fy, &K);
     for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
     int side = wall_side(p, (int)(n / (size_t)p->nx));
-    if (side) wall_close(fn, side, -0.5 * Fx, wall_jy(p));
+    if (side) wall_close(fn, side, -0.5 * Fx, -0.5 * wall_fy(p, w->rho[n]));
     for (int i = 0; i < 9; ++i) {
       jx += fn[i] * CX[i];
       jy += fn[i] * CY[i];
@@ -624,7 +650,7 @@ static void collide_node(const orc_params *p, const double *f, size_t N,
   for (int i = 0; i < 9; ++i) fn[i] = f[i * N + n];
   node_force(p, w, n, &Fx, &Fy, &K);
   int side = wall_side(p, (int)(n / (size_t)p->nx));
-  if (side) wall_close(fn, side, -0.5 * Fx, wall_jy(p));
+  if (side) wall_close(fn, side, -0.5 * Fx, -0.5 * wall_fy(p, rho));
 
   /* Eq. 6b. */
   double jx = 0.0, jy = 0.0;
@@ -661,8 +687,10 @@ static void collide_node(const orc_params *p, const double *f, size_t N,
     double Fi[9], dn[4] = {0.0, 0.0, 0.0, 0.0};
     if (p->A != 0.0)
       for (int k = 0; k < 4; ++k) dn[k] = w->du[k][n];
-    feq_well_balanced(rho, ux, uy, 0.0, p->A, dn, feq); /* Eq. 20, p_g = 0 */
-    forcing_well_balanced(ux, uy, Fx, Fy, w->grx[n], w->gry[n], 0.0, Fi); /* Eq. 21 */
+    /* Eq. 20 and Eq. 21, with p_g and d_y p_g of R10 (zero without gravity) */
+    double pg = pg_row(p, (int)(n / (size_t)p->nx));
+    feq_well_balanced(rho, ux, uy, pg, p->A, dn, feq);
+    forcing_well_balanced(ux, uy, Fx, Fy, w->grx[n], w->gry[n], p->rho0_g * p->g, Fi);
     mat_vec(MM, Fi, mF);
   }
 
