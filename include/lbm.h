@@ -30,7 +30,8 @@
  * enqueued on the HIP stream given to lbm_init() (NULL = the null stream).
  * Only lbm_observe() and the lbm_batch_run() / lbm_batch_observe() calls
  * synchronise that stream.  One context per stream; contexts on different
- * streams are independent.  The library holds no global state.
+ * streams are independent.  The library holds no global state apart from
+ * the fixed device array of lbm_mlp_grad_noalloc (below).
  *
  * Errors.  Every entry point returns an lbm_status.  Invalid arguments are
  * detected on the host before any device work is enqueued and leave all
@@ -371,6 +372,27 @@ lbm_status lbm_mlp_train_step(float* d_params, float* d_m, float* d_v, int64_t t
                               int32_t n_rows, const int32_t* d_idx, int32_t n, float* d_grad,
                               float* d_loss, int32_t flags, void* d_workspace, size_t bytes,
                               void* hip_stream);
+
+/* ---- allocation-free gradient -------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc):
+ * lbm_mlp_grad without the workspace argument.  The per-workgroup gradient
+ * partials live in a fixed device array inside the library (about 8.4 MiB,
+ * the partials of LBM_MLP_NOALLOC_MAX_N samples), one copy per GPU, held
+ * until the process ends; its address is looked up on the first call on
+ * each device.  The call allocates nothing (no hipMalloc, no library
+ * allocator), and its results are identical to lbm_mlp_grad's for the same
+ * arguments.  n > LBM_MLP_NOALLOC_MAX_N returns LBM_ERR_WORKSPACE with no
+ * device work; other arguments and errors as lbm_mlp_grad.  The array is
+ * shared by every call on that GPU: two calls whose work overlaps in time on
+ * one GPU (different streams or threads) race on it and give wrong
+ * results; calls in one stream are ordered and safe. */
+#define LBM_MLP_NOALLOC_MAX_N 1024
+
+lbm_status lbm_mlp_grad_noalloc(const float* d_params, const lbm_mlp_norm* norm,
+                                const float* d_x, const float* d_y, int32_t n_rows,
+                                const int32_t* d_idx, int32_t n, float* d_grad, float* d_loss,
+                                int32_t flags, void* hip_stream);
 
 #ifdef __cplusplus
 }

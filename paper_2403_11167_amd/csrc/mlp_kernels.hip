@@ -29,6 +29,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "lbm.h"
 
 namespace mlpk {
@@ -388,6 +390,78 @@ int grad_blocks(int n) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Workspace layout of a gradient over n samples: per-workgroup gradient
+// slices, then the per-workgroup loss partials.
+size_t part_bytes(int g) { return align256((size_t)g * NPARAM * sizeof(float)); }
+
+lbm_status grad_args_ok(const float* d_params, const lbm_mlp_norm* norm, const float* d_x,
+                        const float* d_y, int32_t n_rows, const int32_t* d_idx, int32_t n,
+                        const float* d_grad, int32_t flags) {
+  if (!d_params || !norm || !d_x || !d_y || !d_grad || n < 1 || n_rows < 1 ||
+      (!d_idx && n > n_rows) || (flags & ~LBM_MLP_BF16))
+    return LBM_ERR_INVALID_ARG;
+  if (!norm_ok(norm)) return LBM_ERR_INVALID_ARG;
+  return LBM_OK;
+}
+
+// The gradient kernels of lbm_mlp_grad on a scratch area `ws` laid out as
+// above (arguments already checked).
+lbm_status grad_launch(const float* d_params, const lbm_mlp_norm* norm, const float* d_x,
+                       const float* d_y, int32_t n_rows, const int32_t* d_idx, int32_t n,
+                       float* d_grad, float* d_loss, int32_t flags, char* ws, hipStream_t st) {
+  const Norm nm = to_norm(norm);
+  const int g = grad_blocks(n);
+  float* part = (float*)ws;
+  float* lpart = (float*)(ws + part_bytes(g));
+  const float scale = 1.0f / (4.0f * (float)n);
+  if (flags & LBM_MLP_BF16)
+    hipLaunchKernelGGL(k_mlp_grad<1>, dim3(g), dim3(NT), 0, st, d_params, nm, d_x, d_y, d_idx,
+                       n, n_rows, scale, part, lpart);
+  else
+    hipLaunchKernelGGL(k_mlp_grad<0>, dim3(g), dim3(NT), 0, st, d_params, nm, d_x, d_y, d_idx,
+                       n, n_rows, scale, part, lpart);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, st, part, lpart, g,
+                     scale, d_grad, d_loss);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+// ---- allocation-free gradient ----------------------------------------------
+// lbm_mlp_grad_noalloc keeps the gradient partials in this file-scope device
+// array instead of a caller workspace: room for the partials of
+// LBM_MLP_NOALLOC_MAX_N samples (64 workgroup slices, about 8.4 MiB).  Every
+// GPU the library runs on holds its own copy until the process ends.  In
+// host code `scratch` is only a host-side stand-in for the symbol; kernels
+// get its device address, looked up once per device below.
+constexpr int NOALLOC_BLOCKS = (LBM_MLP_NOALLOC_MAX_N + TS - 1) / TS;
+static_assert(NOALLOC_BLOCKS <= MAX_GRAD_BLOCKS, "no-alloc bound");
+constexpr size_t NOALLOC_BYTES =
+    ((size_t)NOALLOC_BLOCKS * NPARAM * sizeof(float) + 255) / 256 * 256 +
+    ((size_t)NOALLOC_BLOCKS * sizeof(float) + 255) / 256 * 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev: hipGetSymbolAddress with dev
+// current, on the first call for dev; later calls reuse the stored pointer.
+lbm_status scratch_on(int dev, char** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return LBM_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return LBM_ERR_HIP;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return LBM_ERR_HIP;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) return LBM_ERR_HIP;
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
 }  // namespace mlpk
 
 using namespace mlpk;
@@ -421,29 +495,33 @@ lbm_status lbm_mlp_grad(const float* d_params, const lbm_mlp_norm* norm, const f
                         const float* d_y, int32_t n_rows, const int32_t* d_idx, int32_t n,
                         float* d_grad, float* d_loss, int32_t flags, void* d_workspace,
                         size_t bytes, void* hip_stream) {
-  if (!d_params || !norm || !d_x || !d_y || !d_grad || n < 1 || n_rows < 1 ||
-      (!d_idx && n > n_rows) || (flags & ~LBM_MLP_BF16))
-    return LBM_ERR_INVALID_ARG;
-  if (!norm_ok(norm)) return LBM_ERR_INVALID_ARG;
+  lbm_status s = grad_args_ok(d_params, norm, d_x, d_y, n_rows, d_idx, n, d_grad, flags);
+  if (s != LBM_OK) return s;
   size_t need;
   lbm_mlp_workspace_bytes(n, &need);
   if (!d_workspace || bytes < need || ((uintptr_t)d_workspace % 256) != 0)
     return LBM_ERR_WORKSPACE;
+  return grad_launch(d_params, norm, d_x, d_y, n_rows, d_idx, n, d_grad, d_loss, flags,
+                     (char*)d_workspace, (hipStream_t)hip_stream);
+}
+
+lbm_status lbm_mlp_grad_noalloc(const float* d_params, const lbm_mlp_norm* norm,
+                                const float* d_x, const float* d_y, int32_t n_rows,
+                                const int32_t* d_idx, int32_t n, float* d_grad, float* d_loss,
+                                int32_t flags, void* hip_stream) {
+  lbm_status s = grad_args_ok(d_params, norm, d_x, d_y, n_rows, d_idx, n, d_grad, flags);
+  if (s != LBM_OK) return s;
+  if (n > LBM_MLP_NOALLOC_MAX_N) return LBM_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)hip_stream;
-  const Norm nm = to_norm(norm);
-  const int g = grad_blocks(n);
-  float* part = (float*)d_workspace;
-  float* lpart = (float*)((char*)d_workspace + align256((size_t)g * NPARAM * sizeof(float)));
-  const float scale = 1.0f / (4.0f * (float)n);
-  if (flags & LBM_MLP_BF16)
-    hipLaunchKernelGGL(k_mlp_grad<1>, dim3(g), dim3(NT), 0, st, d_params, nm, d_x, d_y, d_idx,
-                       n, n_rows, scale, part, lpart);
-  else
-    hipLaunchKernelGGL(k_mlp_grad<0>, dim3(g), dim3(NT), 0, st, d_params, nm, d_x, d_y, d_idx,
-                       n, n_rows, scale, part, lpart);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, st, part, lpart, g,
-                     scale, d_grad, d_loss);
-  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+  int dev = -1;
+  if (st) {
+    if (hipStreamGetDevice(st, &dev) != hipSuccess) return LBM_ERR_HIP;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return LBM_ERR_HIP;
+  }
+  char* ws = nullptr;
+  if ((s = scratch_on(dev, &ws)) != LBM_OK) return s;
+  return grad_launch(d_params, norm, d_x, d_y, n_rows, d_idx, n, d_grad, d_loss, flags, ws, st);
 }
 
 lbm_status lbm_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t t,

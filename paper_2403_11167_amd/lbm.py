@@ -34,7 +34,7 @@ EXPORTED_SYMBOLS = [
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_state",
     "lbm_batch_observe", "lbm_batch_destroy", "lbm_batch_set_limit", "lbm_batch_set_partner",
     "lbm_mlp_forward", "lbm_mlp_workspace_bytes", "lbm_mlp_grad", "lbm_mlp_adam",
-    "lbm_mlp_train_step",
+    "lbm_mlp_train_step", "lbm_mlp_grad_noalloc",
 ]
 
 MLP_NPARAMS = 34180
@@ -145,6 +145,7 @@ def lib():
         L.lbm_mlp_forward.argtypes = [vp, NP, vp, i32, vp, i32, vp]
         L.lbm_mlp_workspace_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         L.lbm_mlp_grad.argtypes = [vp, NP, vp, vp, i32, vp, i32, vp, vp, i32, vp, sz, vp]
+        L.lbm_mlp_grad_noalloc.argtypes = [vp, NP, vp, vp, i32, vp, i32, vp, vp, i32, vp]
         L.lbm_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64, f32, f32, f32, f32, vp]
         L.lbm_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int64, f32, NP, vp, vp, i32, vp,
                                          i32, vp, vp, i32, vp, sz, vp]
@@ -484,6 +485,32 @@ def mlp_grad(params, norm: MlpNorm, x, y, idx=None, n=None, bf16: bool = True, s
                               _ptr(idx), int(n), _ptr(grad), _ptr(loss),
                               MLP_BF16 if bf16 else 0, _ptr(ws), ws.numel(), _stream_ptr(st)),
            "lbm_mlp_grad")
+    return loss, grad
+
+
+MLP_NOALLOC_MAX_N = 1024
+
+
+def mlp_grad_noalloc(params, norm: MlpNorm, x, y, idx=None, n=None, bf16: bool = True,
+                     stream=None, out=None):
+    """mlp_grad through lbm_mlp_grad_noalloc (partials in the library's fixed
+    device array, n <= MLP_NOALLOC_MAX_N).  `out` = (loss, grad) tensors to
+    write into (allocated here when None)."""
+    import torch
+    dev = x.device
+    nrows = int(x.shape[0])
+    if n is None:
+        n = int(idx.numel()) if idx is not None else nrows
+    if out is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=dev)
+    else:
+        loss, grad = out
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(lib().lbm_mlp_grad_noalloc(_ptr(params), ctypes.byref(norm), _ptr(x), _ptr(y), nrows,
+                                      _ptr(idx), int(n), _ptr(grad), _ptr(loss),
+                                      MLP_BF16 if bf16 else 0, _stream_ptr(st)),
+           "lbm_mlp_grad_noalloc")
     return loss, grad
 
 
