@@ -76,9 +76,11 @@ typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_precision;
  * rebuilt each step, the normal one equal to its opposite and the two
  * diagonal ones from the momentum -F/2 that u = 0 requires.  The density
  * stencils (psi, mu, grad rho) see mirrored rows past a wall, so the
- * density has no normal gradient there.  Needs ny >= 3 and fy = 0 (the
- * closure conserves mass only without a force normal to the walls); single
- * lattices only (a batch with walls returns LBM_ERR_UNSUPPORTED). */
+ * density has no normal gradient there.  A force normal to the walls (fy,
+ * gravity) enters the closure through -F/2; the wall density then carries
+ * the normal momentum (+j_y on the bottom wall, -j_y on the top one).  Needs
+ * ny >= 3; single lattices only (a batch with walls returns
+ * LBM_ERR_UNSUPPORTED). */
 typedef enum { LBM_BOUNDARY_PERIODIC = 0, LBM_BOUNDARY_WALLS = 1 } lbm_boundary;
 
 /* Sticky device flags (lbm_obs.flags). */
@@ -113,8 +115,7 @@ typedef struct {
                            (S = grad u + grad u^T with the Eq. 24 stencil;
                            past a wall u is reflected with its sign flipped);
                            P: LBM_ERR_UNSUPPORTED; batches: unsupported    */
-  double fx, fy;        /* constant body force added to the model force
-                           (with walls fy must be 0: LBM_ERR_UNSUPPORTED)  */
+  double fx, fy;        /* constant body force added to the model force     */
   double rho_ref;       /* FP32_SHIFTED: reference density of the storage
                            shift (<= 0: the smallest initial density)       */
   /* Launch shape; 0 selects the tuned default (see lbm_autotune).  Results
@@ -125,6 +126,9 @@ typedef struct {
                            of resident workgroups (at least 16 rows)        */
   int32_t kernel_flags; /* 0, or LBM_KF_SET | any of the LBM_KF_* below
                            (with walls: ignored, non-temporal stores only) */
+  int32_t tile_rounds;  /* with tile_y = 0: the rounds of resident
+                           workgroups the tiles fill, 0 .. 64 (0: 3 for the
+                           pseudopotential, 1 for the free energy)          */
   /* Droplet-collision drive (Sec. 5.4): an x force a(x) |rho - rho_ave|
      added to fx, with a = +ax for x <= x_split and -ax beyond, in the steps
      that start at t >= ax_from_step (the paper: a_x = 5e-6, x_split = 100 on
@@ -135,12 +139,28 @@ typedef struct {
   double rho_ave;       /* <= 0: the mean of the initial density (the scheme
                            conserves mass, so the mean stays constant)      */
   int64_t ax_from_step; /* >= 0                                              */
+  /* Gravity of the free-energy model (Sec. 2.2): p_g = grav_rho0 g
+     (y - grav_y0) in the equilibrium of Eq. 20 (also at t = 0), the
+     buoyancy F_g = -(rho - grav_rho0) g in y added to the force, and
+     d_y p_g = grav_rho0 g in the forcing of Eq. 21; g > 0 pulls toward -y
+     (the momentum gains -d_y p_g + F_g = -rho g).  g = 0 turns it off.
+     Needs LBM_BOUNDARY_WALLS (p_g is not periodic), |g| < 1 and
+     grav_rho0 >= 0, else LBM_ERR_INVALID_ARG; the pseudopotential model and
+     batches return LBM_ERR_UNSUPPORTED.  On a wall row the normal force is
+     fy + F_g of the wall node's density.  The row grav_y0 where p_g = 0
+     only moves rounding: results do not depend on it otherwise. */
+  double g;
+  double grav_rho0;
+  double grav_y0;
 } lbm_params;
 
 #define LBM_KF_SET 0x80000000u  /* kernel_flags given explicitly            */
 #define LBM_KF_NT_STORE 1u      /* non-temporal population stores           */
 #define LBM_KF_REGCAP 2u        /* register-capped kernel, higher occupancy */
 #define LBM_KF_PIPELINE 4u      /* software-pipelined row loop (P only)     */
+#define LBM_KF_NO_XCD_REMAP 8u  /* keep the dispatch order of the tiles
+                                   (default: a contiguous band of tiles per
+                                   XCD, whose L2 the neighbours share)      */
 
 /* Observables of the current state (Eq. 6a-b and Sec. 5.2). */
 typedef struct {

@@ -67,6 +67,9 @@ struct KParams {
   C ax, rho_ave;   // droplet-collision drive a(x) |rho - rho_ave| (0: off now)
   int x_split;     // a = +ax for x <= x_split, -ax beyond
   C A;             // FE: viscosity-tuning A of Eq. 20 (0: off)
+  C g, grho0, gy0; // FE gravity (Sec. 2.2): p_g = grho0 g (y - gy0) in Eq. 20,
+                   // buoyancy -(rho - grho0) g in y, d_y p_g = grho0 g in Eq. 21
+                   // (g = 0: off; walls only)
   double* uax;     // FE with A != 0: velocity field of the current step
   double* uay;
   C rho_ref;       // sum of the storage shift s_i
@@ -295,11 +298,18 @@ __device__ __forceinline__ void gather(const C* bot, const C* mid, const C* top,
 // Eq. 21 (FE), mC of Eq. 13 (P).  The j rows reduce exactly to j + F.
 // With AV = 1 (free energy) the equilibrium also carries the A terms of
 // Eq. 20: a_div = rho A div(u) and a_xx, a_xy, their p_xx and p_xy moments.
+//
+// FE with gravity (Sec. 2.2): pg = p_g at the node adds w_i p_g / c_s^2
+// (i > 0) and -(1 - w_0) p_g / c_s^2 (i = 0) to the equilibrium, whose
+// moments are e 6 p_g and zeta -9 p_g; dpg = d_y p_g replaces F_y by
+// F_y - d_y p_g in the velocity-dependent part of Eq. 21, which moves the
+// e / zeta forcing by -/+ 6 u_y dpg, p_xx by 2 u_y dpg and p_xy by -u_x dpg.
 template <int MODEL, int AV = 0, class C>
 __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
                                         C t0, C t1, C t2, C t3,
                                         const KParams<C>& kp, C& ux_out, C& uy_out,
-                                        C a_div = C(0), C a_xx = C(0), C a_xy = C(0)) {
+                                        C a_div = C(0), C a_xx = C(0), C a_xy = C(0),
+                                        C pg = C(0), C dpg = C(0)) {
   // P: t0 = G^2 |S|^2, t1 = Qxx + Qyy, t2 = Qxx - Qyy, t3 = Qxy.
   // FE: t0 = d_x rho, t1 = d_y rho.
   C jx = (g[1] - g[3]) + ((g[5] - g[7]) - (g[6] - g[8]));
@@ -342,6 +352,10 @@ __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
     eqpxx += a_xx;
     eqpxy += a_xy;
   }
+  if constexpr (MODEL == MODEL_FE) {
+    eqe += C(6) * pg;
+    eqz -= C(9) * pg;
+  }
 
   C uF = ux * Fx + uy * Fy;
   C Fe, Fz, Fpxx, Fpxy;
@@ -357,10 +371,10 @@ __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
     Cpxy = -t3 * kp.lam_nu;
   } else {
     C ug = ux * t0 + uy * t1;
-    Fe = C(6) * uF + C(4) * ug;
+    Fe = C(6) * uF + C(4) * ug - C(6) * uy * dpg;
     Fz = -Fe;
-    Fpxx = C(2) * (ux * Fx - uy * Fy) + C(2.0 / 3.0) * (ux * t0 - uy * t1);
-    Fpxy = ux * Fy + uy * Fx + C(1.0 / 3.0) * (ux * t1 + uy * t0);
+    Fpxx = C(2) * (ux * Fx - uy * Fy) + C(2.0 / 3.0) * (ux * t0 - uy * t1) + C(2) * uy * dpg;
+    Fpxy = ux * Fy + uy * Fx + C(1.0 / 3.0) * (ux * t1 + uy * t0) - ux * dpg;
   }
 
   C se = me - kp.lam_e * (me - eqe) + kp.hl_e * Fe + Ce;
@@ -466,6 +480,29 @@ __device__ __forceinline__ void wall_fill(C g[9], int side, C fy) {
   g[4] = b ? g[4] : s4;
   g[7] = b ? g[7] : s7;
   g[8] = b ? g[8] : s8;
+}
+
+// Closure of a free-energy wall row, whose normal force is fy plus, with
+// gravity, the buoyancy -(rho - rho_0) g of its own density: the density
+// with the normal part closed at zero, r0, moves by side j_y with
+// j_y = -F_y(rho)/2, a linear equation for rho.  Without gravity this is
+// wall_fill with fy.
+template <class C>
+__device__ __forceinline__ void wall_fill_fe(C g[9], int side, const KParams<C>& kp) {
+  C fy = kp.fy;
+  if (kp.g != C(0)) {
+    // r0: the known populations plus the unknowns closed at j_y = 0 (the
+    // normal one equals its opposite, the diagonal pair sums to the pair
+    // opposite it): g0 + g1 + g3 + 2 (g4 + g7 + g8) on the bottom wall,
+    // g0 + g1 + g3 + 2 (g2 + g5 + g6) on the top one
+    const bool b = side > 0;
+    const C in = b ? (g[4] + g[7]) + g[8] : (g[2] + g[5]) + g[6];
+    const C r0 = kp.rho_ref + ((g[0] + (g[1] + g[3])) + C(2) * in);
+    const C sd = b ? C(1) : C(-1);
+    const C rho = (r0 - sd * C(0.5) * (kp.fy + kp.g * kp.grho0)) / (C(1) - sd * C(0.5) * kp.g);
+    fy = kp.fy - (rho - kp.grho0) * kp.g;
+  }
+  wall_fill(g, side, fy);
 }
 
 template <class C>
@@ -861,13 +898,13 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
     if (hr) pull9<S, C, NT>(src, rm, r0, rp, hcm, hc0, hcp, h);
     if (active) {
       pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
-      if (GEN != 0 && sd) wall_fill(g, sd, kp.fy);
+      if (GEN != 0 && sd) wall_fill_fe(g, sd, kp);
       dr = sum9(g);
       fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dr, kp);
       row[t + 2] = dr;
     }
     if (hr) {
-      if (GEN != 0 && sd) wall_fill(h, sd, kp.fy);
+      if (GEN != 0 && sd) wall_fill_fe(h, sd, kp);
       row[hj] = sum9(h);
     }
   };
@@ -928,8 +965,12 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
         if (sd) {
           Fy = kp.fy;
           gry = C(0);
-          wall_fx(g0, sd, Fx);
         }
+        // gravity: the buoyancy joins the force (on a wall row too)
+        if (kp.g != C(0)) Fy -= (rho - kp.grho0) * kp.g;
+        if (sd) wall_fx(g0, sd, Fx);
+        const C pg = kp.grho0 * kp.g * (C(y) - kp.gy0);
+        const C dpg = kp.grho0 * kp.g;
         if constexpr (GEN == 2) {
           const C jx = (g0[1] - g0[3]) + ((g0[5] - g0[7]) - (g0[6] - g0[8]));
           const C jy = (g0[2] - g0[4]) + ((g0[5] - g0[7]) + (g0[6] - g0[8]));
@@ -949,10 +990,11 @@ __device__ __forceinline__ void tile_fe(const S* __restrict__ src, S* __restrict
           a_xy = C(1.0 / 3.0) * ra * (dxuy + dyux);
         }
         if constexpr (GEN == 1)
-          collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
+          collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy, C(0), C(0),
+                            C(0), pg, dpg);
         if constexpr (GEN == 3)
           collide<MODEL_FE, 1>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy, a_div,
-                               a_xx, a_xy);
+                               a_xx, a_xy, pg, dpg);
       } else {
         collide<MODEL_FE>(g0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
       }
@@ -1195,9 +1237,12 @@ void k_batch_step(const BatchTile* __restrict__ tiles, const InstDesc<C>* __rest
 // ---- initial state ------------------------------------------------------------
 // Stored g*_i(x) = f^eq_i(rho0(x + c_i), 0) - s_i, so that the first pull
 // yields f_i(x) = f^eq_i(rho0(x), 0) (Eq. 4: w_i rho; Eq. 20: rho delta_i0).
+// FE with gravity: f^eq also carries the p_g terms of Eq. 20, with
+// p_g / c_s^2 = pg1 (y - gy0) on row y (pg1 = grho0 g / c_s^2).
 template <int MODEL, class S>
 __global__ void k_init(const double* __restrict__ rho0, S* __restrict__ dst,
-                       int nx, int ny, int rowpitch, double s0, double sax, double sdg) {
+                       int nx, int ny, int rowpitch, double s0, double sax, double sdg,
+                       double pg1 = 0.0, double gy0 = 0.0) {
   const size_t N = (size_t)nx * ny;
   const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -1210,6 +1255,11 @@ __global__ void k_init(const double* __restrict__ rho0, S* __restrict__ dst,
       int xs = wrapi(x + cx[i], nx), ys = wrapi(y + cy[i], ny);
       double r = rho0[(size_t)ys * nx + xs];
       double feq = (MODEL == MODEL_P) ? wt[i] * r : ((i == 0) ? r : 0.0);
+      if (MODEL == MODEL_FE && pg1 != 0.0) {
+        // p_g / c_s^2 of the node the population streams to
+        const double q = pg1 * ((double)ys - gy0);
+        feq += (i == 0) ? -(1.0 - wt[0]) * q : wt[i] * q;
+      }
       double s = (i == 0) ? s0 : (i < 5 ? sax : sdg);
       dst[y * rowpitch + colo(x) + 64 * i] = (S)(feq - s);
     }
@@ -1272,7 +1322,7 @@ __global__ void k_obs_rho(const S* __restrict__ src, const KParams<double> kp,
     double g[9];
     pull9(src, rm, r0, rp, colo(xm), colo(x), colo(xp), g);
     const int sd = kp.walls ? wall_side(y, ny) : 0;
-    if (sd) wall_fill(g, sd, kp.fy);
+    if (sd) wall_fill_fe(g, sd, kp);  // kp.g = 0 for the pseudopotential
     double rho = kp.rho_ref + sum9(g);
     fl |= domain_flags<MODEL, EOS>(rho, kp);
     rho_w[n] = rho;
@@ -1324,6 +1374,56 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
   e = (a - (s - bb)) + (b - bb);
 }
 
+// Combine two partials: compensated sum (two_sum is exact and symmetric, so
+// both partners of a butterfly get bit-identical results), maxima, and a
+// minimum that stays NaN once a NaN density was seen.
+__device__ __forceinline__ ObsPartial obs_combine(const ObsPartial& a, const ObsPartial& b) {
+  ObsPartial r;
+  double s, e;
+  two_sum(a.sum_hi, b.sum_hi, s, e);
+  r.sum_hi = s;
+  r.sum_lo = (a.sum_lo + b.sum_lo) + e;
+  r.max_u = fmax(a.max_u, b.max_u);
+  r.rho_min = (a.rho_min != a.rho_min || b.rho_min != b.rho_min) ? NAN : fmin(a.rho_min, b.rho_min);
+  r.rho_max = fmax(a.rho_max, b.rho_max);
+  r.du_max = fmax(a.du_max, b.du_max);
+  r.pad0 = r.pad1 = 0.0;
+  return r;
+}
+
+__device__ __forceinline__ ObsPartial obs_shfl_xor(const ObsPartial& a, int off) {
+  ObsPartial b;
+  b.sum_hi = __shfl_xor(a.sum_hi, off, 64);
+  b.sum_lo = __shfl_xor(a.sum_lo, off, 64);
+  b.max_u = __shfl_xor(a.max_u, off, 64);
+  b.rho_min = __shfl_xor(a.rho_min, off, 64);
+  b.rho_max = __shfl_xor(a.rho_max, off, 64);
+  b.du_max = __shfl_xor(a.du_max, off, 64);
+  b.pad0 = b.pad1 = 0.0;
+  return b;
+}
+
+// Block reduction of one partial per thread: a butterfly of wavefront
+// shuffles (every lane ends with the wavefront's result), one partial per
+// wavefront through LDS, then the same butterfly in the first wavefront.
+// The combination order is fixed, so the result is deterministic.  Returns
+// the block's partial in thread 0.
+template <int NT>
+__device__ __forceinline__ ObsPartial obs_block_reduce(ObsPartial a) {
+  static_assert(NT % 64 == 0 && NT <= 64 * 64, "block of whole wavefronts");
+  __shared__ ObsPartial sh[NT / 64];
+  for (int off = 32; off > 0; off >>= 1) a = obs_combine(a, obs_shfl_xor(a, off));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = a;
+  __syncthreads();
+  if (wave == 0) {
+    a = lane < NT / 64 ? sh[lane]
+                       : ObsPartial{0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0, 0.0};
+    for (int off = 32; off > 0; off >>= 1) a = obs_combine(a, obs_shfl_xor(a, off));
+  }
+  return a;
+}
+
 // Pass 3: force, velocity (Eq. 6b), exports, per-block partial reductions.
 template <int MODEL, class S, int NT>
 __global__ __launch_bounds__(NT) void k_obs_u(
@@ -1344,7 +1444,7 @@ __global__ __launch_bounds__(NT) void k_obs_u(
     double g[9];
     pull9(src, rm, r0, rp, colo(xm), colo(x), colo(xp), g);
     const int sd = kp.walls ? wall_side(y, ny) : 0;
-    if (sd) wall_fill(g, sd, kp.fy);
+    if (sd) wall_fill_fe(g, sd, kp);
     double rho = rho_w[n];
     double Fx, Fy;
     if (MODEL == MODEL_P) {
@@ -1361,10 +1461,9 @@ __global__ __launch_bounds__(NT) void k_obs_u(
       Fy = -rho * sy + kp.fy;
     }
     if (kp.ax != 0.0) Fx += drive_fx(kp, x, rho);
-    if (sd) {
-      Fy = kp.fy;  // zero normal interaction force on a wall row
-      wall_fx(g, sd, Fx);
-    }
+    if (sd) Fy = kp.fy;  // zero normal interaction force on a wall row
+    if (kp.g != 0.0) Fy -= (rho - kp.grho0) * kp.g;  // buoyancy (FE gravity)
+    if (sd) wall_fx(g, sd, Fx);
     double jx = (g[1] - g[3]) + ((g[5] - g[7]) - (g[6] - g[8]));
     double jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
     double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho;
@@ -1383,29 +1482,13 @@ __global__ __launch_bounds__(NT) void k_obs_u(
     s_hi = s;
     s_lo += e;
     mu = fmax(mu, sqrt(ux * ux + uy * uy));
-    rmin = fmin(rmin, rho);
+    // rho_min stays NaN once a non-finite density was seen (fmin would drop it)
+    rmin = (rmin != rmin || !__builtin_isfinite(rho)) ? NAN : fmin(rmin, rho);
     rmax = fmax(rmax, rho);
-    if (!__builtin_isfinite(rho)) rmin = NAN;
   }
-  __shared__ ObsPartial sh[NT];
-  sh[threadIdx.x] = ObsPartial{s_hi, s_lo, mu, rmin, rmax, du, 0.0, 0.0};
-  __syncthreads();
-  for (int stride = NT / 2; stride > 0; stride >>= 1) {
-    if ((int)threadIdx.x < stride) {
-      ObsPartial a = sh[threadIdx.x], b = sh[threadIdx.x + stride];
-      double s, e;
-      two_sum(a.sum_hi, b.sum_hi, s, e);
-      a.sum_hi = s;
-      a.sum_lo = a.sum_lo + b.sum_lo + e;
-      a.max_u = fmax(a.max_u, b.max_u);
-      a.rho_min = (a.rho_min != a.rho_min || b.rho_min != b.rho_min) ? NAN : fmin(a.rho_min, b.rho_min);
-      a.rho_max = fmax(a.rho_max, b.rho_max);
-      a.du_max = fmax(a.du_max, b.du_max);
-      sh[threadIdx.x] = a;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+  const ObsPartial blk =
+      obs_block_reduce<NT>(ObsPartial{s_hi, s_lo, mu, rmin, rmax, du, 0.0, 0.0});
+  if (threadIdx.x == 0) part[blockIdx.x] = blk;
 }
 
 // Pass 4: one workgroup combines the partials in a fixed order and forms the
@@ -1414,42 +1497,11 @@ template <int EOS, int NT>
 __global__ __launch_bounds__(NT) void k_obs_final(
     const ObsPartial* __restrict__ part, int nparts, const KParams<double> kp,
     const double* __restrict__ rho_w, int cx, int cy, double* __restrict__ res) {
-  __shared__ ObsPartial sh[NT];
   ObsPartial acc{0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0, 0.0};
-  bool nan_min = false;
-  for (int i = threadIdx.x; i < nparts; i += NT) {
-    ObsPartial b = part[i];
-    double s, e;
-    two_sum(acc.sum_hi, b.sum_hi, s, e);
-    acc.sum_hi = s;
-    acc.sum_lo += b.sum_lo + e;
-    acc.max_u = fmax(acc.max_u, b.max_u);
-    if (b.rho_min != b.rho_min) nan_min = true;
-    acc.rho_min = fmin(acc.rho_min, b.rho_min);
-    acc.rho_max = fmax(acc.rho_max, b.rho_max);
-    acc.du_max = fmax(acc.du_max, b.du_max);
-  }
-  if (nan_min) acc.rho_min = NAN;
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int stride = NT / 2; stride > 0; stride >>= 1) {
-    if ((int)threadIdx.x < stride) {
-      ObsPartial a = sh[threadIdx.x], b = sh[threadIdx.x + stride];
-      double s, e;
-      two_sum(a.sum_hi, b.sum_hi, s, e);
-      a.sum_hi = s;
-      a.sum_lo = a.sum_lo + b.sum_lo + e;
-      a.max_u = fmax(a.max_u, b.max_u);
-      a.rho_min = (a.rho_min != a.rho_min || b.rho_min != b.rho_min) ? NAN : fmin(a.rho_min, b.rho_min);
-      a.rho_max = fmax(a.rho_max, b.rho_max);
-      a.du_max = fmax(a.du_max, b.du_max);
-      sh[threadIdx.x] = a;
-    }
-    __syncthreads();
-  }
+  for (int i = threadIdx.x; i < nparts; i += NT) acc = obs_combine(acc, part[i]);
+  const ObsPartial a = obs_block_reduce<NT>(acc);
   if (threadIdx.x == 0) {
     const int nx = kp.nx, ny = kp.ny;
-    ObsPartial a = sh[0];
     double mass = a.sum_hi + a.sum_lo;
     int xi = wrapi(cx, nx), yi = wrapi(cy, ny);
     int xo = wrapi(cx + nx / 2, nx), yo = wrapi(cy + ny / 2, ny);
@@ -1482,6 +1534,7 @@ using namespace lbmk;
 namespace {
 
 constexpr int kObsThreads = 256;
+constexpr int kGraphSteps = 16;  // steps per graph run of lbm_step (even)
 constexpr int kObsBlocksMax = 2048;
 constexpr size_t kAlign = 256;
 
@@ -1549,9 +1602,14 @@ lbm_status validate(const lbm_params* p) {
     if (p->model != LBM_MODEL_FE) return LBM_ERR_UNSUPPORTED;
     if (!(p->tau[7] - 0.5 - p->A > 0.0)) return LBM_ERR_INVALID_ARG;
   }
-  // Zou-He walls hold u = 0 under a tangential force only: with a normal
-  // body force the closure does not conserve mass
-  if (p->boundary == LBM_BOUNDARY_WALLS && p->fy != 0.0) return LBM_ERR_UNSUPPORTED;
+  if (!finite(p->g) || !finite(p->grav_rho0) || !finite(p->grav_y0)) return LBM_ERR_INVALID_ARG;
+  if (p->g != 0.0) {
+    // gravity of the free-energy model (Sec. 2.2); p_g is not periodic
+    if (p->model != LBM_MODEL_FE) return LBM_ERR_UNSUPPORTED;
+    if (p->boundary != LBM_BOUNDARY_WALLS || p->grav_rho0 < 0.0) return LBM_ERR_INVALID_ARG;
+    // the wall-density relation divides by 1 -+ g/2
+    if (!(std::fabs(p->g) < 1.0)) return LBM_ERR_INVALID_ARG;
+  }
   return LBM_OK;
 }
 
@@ -1597,6 +1655,9 @@ KParams<C> make_kparams(const lbm_params* p, double rho_ref, int nstrips,
   k.ax = (C)0;  // the drive is switched on per step (set_drive)
   k.x_split = p->x_split;
   k.A = (C)p->A;
+  k.g = (C)p->g;
+  k.grho0 = (C)p->grav_rho0;
+  k.gy0 = (C)p->grav_y0;
   k.uax = k.uay = nullptr;
   // rho_ref is chosen by lbm_init so that every shift value below is exact
   // in float and M s is exact (rho_ref = 36 q for P with q a short float).
@@ -1621,12 +1682,6 @@ KParams<C> make_kparams(const lbm_params* p, double rho_ref, int nstrips,
   k.inv_om_ref = (C)(1.0 / om_ref);
   k.inv_om_ref3 = (C)(1.0 / (om_ref * om_ref * om_ref));
   return k;
-}
-
-int env_int(const char* name, int dflt) {
-  const char* v = getenv(name);
-  if (!v || !*v) return dflt;
-  return atoi(v);
 }
 
 // Launch shape of one lattice.
@@ -1655,24 +1710,28 @@ struct lbm_ctx {
   int nstrips, nseg, xcd_remap;
   KParams<double> kd;
   KParams<float> kf;
+  // lbm_step replays runs of kGraphSteps steps as HIP graphs, captured on a
+  // library stream (the caller's may be the null stream) per starting
+  // population buffer and drive state
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  ~lbm_ctx();
 };
 
 namespace {
 
-// Launch-shape resolution: explicit fields of lbm_params first, then the
-// LBM_TILE_X / LBM_LY / LBM_NT / LBM_WPE / LBM_PIPE / LBM_ROUNDS environment
-// overrides (tuning experiments), then defaults measured on MI355X (4096^2
-// lattices: 256-column strips, non-temporal stores, the pipelined
-// pseudopotential kernel without a register cap, the register-capped
-// free-energy kernel, pipelined in FP32; 64-column strips for lattices
-// narrower than 256).  Without an explicit
+// Launch-shape resolution: the launch fields of lbm_params where set, else
+// defaults measured on MI355X (4096^2 lattices: 256-column strips,
+// non-temporal stores, the pipelined pseudopotential kernel without a
+// register cap, the register-capped free-energy kernel, pipelined in FP32;
+// 64-column strips for lattices narrower than 256).  Without an explicit
 // segment height, a single lattice gets one chosen at its first launch so
-// that all tiles run as one round of resident workgroups (see tune_ly); the
-// fallback here (batches) aims at a few thousand tiles.
+// that its tiles fill whole rounds of resident workgroups (see tune_ly);
+// the fallback here (batches) aims at a few thousand tiles.
 LaunchCfg resolve_launch(const lbm_params* p) {
   const bool fp64 = p->precision == LBM_FP64;
   LaunchCfg lc{};
-  lc.bx = p->tile_x ? p->tile_x : env_int("LBM_TILE_X", p->nx < 256 ? 64 : 256);
+  lc.bx = p->tile_x ? p->tile_x : (p->nx < 256 ? 64 : 256);
   if (lc.bx != 64) lc.bx = 256;
   unsigned kf = (unsigned)p->kernel_flags;
   if (kf & LBM_KF_SET) {
@@ -1680,11 +1739,11 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     lc.wpe = (kf & LBM_KF_REGCAP) ? 1 : 0;
     lc.pipe = (kf & LBM_KF_PIPELINE) ? 1 : 0;
   } else {
-    lc.nt = env_int("LBM_NT", 1) ? 1 : 0;
-    lc.wpe = env_int("LBM_WPE", p->model == LBM_MODEL_P ? 0 : 1) ? 1 : 0;
+    lc.nt = 1;
+    lc.wpe = p->model == LBM_MODEL_P ? 0 : 1;
     // pipelined row loop: pseudopotential always; free energy in FP32 only
     // (in FP64 its four live population rows cost a wave of occupancy)
-    lc.pipe = env_int("LBM_PIPE", (p->model == LBM_MODEL_P || !fp64) ? 1 : 0) ? 1 : 0;
+    lc.pipe = (p->model == LBM_MODEL_P || !fp64) ? 1 : 0;
   }
   if (p->boundary == LBM_BOUNDARY_WALLS || p->ax != 0.0 || p->A != 0.0) {
     // walls, the collision drive and A != 0 run in the general kernel:
@@ -1694,8 +1753,8 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     lc.pipe = 0;
   }
   int nstrips = (p->nx + lc.bx - 1) / lc.bx;
-  int LY = p->tile_y ? p->tile_y : env_int("LBM_LY", 0);
-  lc.auto_ly = (LY <= 0 && env_int("LBM_ROUNDS", 1) > 0) ? 1 : 0;
+  int LY = p->tile_y;
+  lc.auto_ly = LY <= 0 ? 1 : 0;
   if (LY <= 0) {
     // enough tiles to fill 256 CUs several times over, segments of at
     // least 8 rows so the two halo rows stay a small overhead
@@ -1711,6 +1770,7 @@ LaunchCfg resolve_launch(const lbm_params* p) {
 lbm_status validate_launch(const lbm_params* p) {
   if (p->tile_x != 0 && p->tile_x != 64 && p->tile_x != 256) return LBM_ERR_INVALID_ARG;
   if (p->tile_y < 0 || p->tile_y > 1024) return LBM_ERR_INVALID_ARG;
+  if (p->tile_rounds < 0 || p->tile_rounds > 64) return LBM_ERR_INVALID_ARG;
   if (p->kernel_flags != 0 && !((unsigned)p->kernel_flags & LBM_KF_SET)) return LBM_ERR_INVALID_ARG;
   if (!std::isfinite(p->ax) || !std::isfinite(p->rho_ave) || p->ax_from_step < 0)
     return LBM_ERR_INVALID_ARG;
@@ -1721,7 +1781,9 @@ void apply_launch(lbm_ctx* c) {
   c->nstrips = (c->p.nx + c->lc.bx - 1) / c->lc.bx;
   c->nseg = (c->p.ny + c->lc.ly - 1) / c->lc.ly;
   int ntiles = c->nstrips * c->nseg;
-  c->xcd_remap = (ntiles >= 64 && ntiles % 8 == 0 && env_int("LBM_NO_XCD_REMAP", 0) == 0) ? 1 : 0;
+  const bool no_remap = ((unsigned)c->p.kernel_flags & LBM_KF_SET) &&
+                        ((unsigned)c->p.kernel_flags & LBM_KF_NO_XCD_REMAP);
+  c->xcd_remap = (ntiles >= 64 && ntiles % 8 == 0 && !no_remap) ? 1 : 0;
   for (KParams<double>* k : {&c->kd}) {
     k->nstrips = c->nstrips;
     k->nseg = c->nseg;
@@ -1752,7 +1814,8 @@ void tune_ly(lbm_ctx* c, K kernel, int bx) {
   }
   // measured on 4096^2: the free-energy kernel is fastest with one round,
   // the pseudopotential kernel with about three
-  const int rounds = env_int("LBM_ROUNDS", c->p.model == LBM_MODEL_P ? 3 : 1);
+  const int rounds = c->p.tile_rounds > 0 ? c->p.tile_rounds
+                                         : (c->p.model == LBM_MODEL_P ? 3 : 1);
   const int resident = blocks * cus * std::max(1, rounds);
   const int segs = std::max(1, resident / c->nstrips);
   int LY = (c->p.ny + segs - 1) / segs;
@@ -1831,6 +1894,7 @@ void launch_step_gen(lbm_ctx* c, const KParams<C>& kp) {
 }
 
 bool needs_gen(const lbm_params& p) {
+  // walls (and with them gravity), the collision drive and A != 0
   return p.boundary == LBM_BOUNDARY_WALLS || p.ax != 0.0 || p.A != 0.0;
 }
 
@@ -1884,7 +1948,8 @@ void launch_init(lbm_ctx* c, const double* rho0) {
                        rho0, dst, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg);
   else
     hipLaunchKernelGGL((k_init<MODEL_FE, S>), dim3(grid1d(N)), dim3(256), 0, c->stream,
-                       rho0, dst, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg);
+                       rho0, dst, c->p.nx, c->p.ny, c->kd.rowpitch, c->kd.s0, c->kd.sax, c->kd.sdg,
+                       3.0 * c->p.grav_rho0 * c->p.g, c->p.grav_y0);
 }
 
 template <int MODEL, int EOS, class S>
@@ -2041,7 +2106,49 @@ lbm_status observe_impl(lbm_ctx* c, int32_t cx, int32_t cy, lbm_obs* out,
   return LBM_OK;
 }
 
+// Run kGraphSteps steps (an even number, so the state ends in the buffer it
+// started from) as one HIP graph: captured once per starting buffer and
+// drive state on the library's capture stream, then launched on the
+// context's stream.  The kernels' arguments (buffers, parameters, launch
+// shape) are recorded by value; they do not change once the first step has
+// fixed the launch shape.
+lbm_status launch_graph_run(lbm_ctx* c) {
+  const int cur0 = c->cur;
+  const int drv = c->kd.ax != 0.0 ? 1 : 0;
+  hipGraphExec_t& ge = c->graph[cur0][drv];
+  if (!ge) {
+    if (!c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+      c->cap = nullptr;
+      return LBM_ERR_HIP;
+    }
+    hipStream_t user = c->stream;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return LBM_ERR_HIP;
+    c->stream = c->cap;
+    for (int k = 0; k < kGraphSteps; ++k) step_once(c);
+    c->stream = user;
+    c->cur = cur0;  // the capture only recorded the launches
+    hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      ge = nullptr;
+      return LBM_ERR_HIP;
+    }
+  }
+  return hipGraphLaunch(ge, c->stream) == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
 }  // namespace
+
+lbm_ctx::~lbm_ctx() {
+  for (auto& row : graph)
+    for (hipGraphExec_t& g : row)
+      if (g) (void)hipGraphExecDestroy(g);
+  if (cap) (void)hipStreamDestroy(cap);
+}
 
 extern "C" {
 
@@ -2084,11 +2191,26 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t bytes,
 
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c || n < 0) return LBM_ERR_INVALID_ARG;
-  for (int64_t k = 0; k < n; ++k) {
-    set_drive(c, c->step + k);
-    step_once(c);
+  lbm_status st = LBM_OK;
+  int64_t k = 0;
+  while (k < n && st == LBM_OK) {
+    const int64_t t = c->step + k;
+    // a whole graph run needs the launch shape fixed (after the first
+    // launch) and one drive state throughout
+    const bool drive_const = c->p.ax == 0.0 || t >= c->p.ax_from_step ||
+                             t + kGraphSteps <= c->p.ax_from_step;
+    if (n - k >= kGraphSteps && !c->lc.auto_ly && drive_const) {
+      set_drive(c, t);
+      st = launch_graph_run(c);
+      k += kGraphSteps;
+    } else {
+      set_drive(c, t);
+      step_once(c);
+      k += 1;
+    }
   }
-  c->step += n;
+  c->step += k;
+  if (st != LBM_OK) return st;
   if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
   return LBM_OK;
 }
@@ -2128,7 +2250,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* d_f) {
 
 lbm_status lbm_destroy(lbm_ctx* c) {
   if (!c) return LBM_ERR_INVALID_ARG;
-  delete c;
+  delete c;  // ~lbm_ctx releases the graphs and the capture stream
   return LBM_OK;
 }
 
@@ -2432,7 +2554,8 @@ lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, size_t* byt
     if (st != LBM_OK) return st;
     if ((st = validate_launch(&p[i])) != LBM_OK) return st;
     if (p[i].precision != p[0].precision) return LBM_ERR_INVALID_ARG;
-    if (p[i].boundary != LBM_BOUNDARY_PERIODIC || p[i].ax != 0.0 || p[i].A != 0.0)
+    if (p[i].boundary != LBM_BOUNDARY_PERIODIC || p[i].ax != 0.0 || p[i].A != 0.0 ||
+        p[i].g != 0.0)
       return LBM_ERR_UNSUPPORTED;
   }
   *bytes = make_batch_layout(n, p).total;

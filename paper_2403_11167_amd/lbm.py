@@ -24,7 +24,7 @@ BOUNDARY_PERIODIC, BOUNDARY_WALLS = 0, 1
 FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
 
 BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS, BATCH_DROPPED = 0, 1, 2, 3, 4
-KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE = 0x80000000, 1, 2, 4
+KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE, KF_NO_XCD_REMAP = 0x80000000, 1, 2, 4, 8
 
 EXPORTED_SYMBOLS = [
     "lbm_status_string", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe",
@@ -59,9 +59,11 @@ class Params(ctypes.Structure):
                 ("A", ctypes.c_double), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
                 ("rho_ref", ctypes.c_double),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("kernel_flags", ctypes.c_uint32), ("x_split", ctypes.c_int32),
+                ("kernel_flags", ctypes.c_uint32), ("tile_rounds", ctypes.c_int32),
+                ("x_split", ctypes.c_int32),
                 ("ax", ctypes.c_double), ("rho_ave", ctypes.c_double),
-                ("ax_from_step", ctypes.c_int64)]
+                ("ax_from_step", ctypes.c_int64), ("g", ctypes.c_double),
+                ("grav_rho0", ctypes.c_double), ("grav_y0", ctypes.c_double)]
 
 
 class MlpNorm(ctypes.Structure):
@@ -237,12 +239,17 @@ class Config:
     tile_x: int = 0
     tile_y: int = 0
     kernel_flags: int = 0
+    tile_rounds: int = 0
     walls: bool = False  # Zou-He no-slip walls on the rows y = 0 and ny - 1
     # droplet-collision drive a(x) |rho - rho_ave| (Sec. 5.4)
     ax: float = 0.0
     x_split: int = 0
     rho_ave: float = 0.0
     ax_from_step: int = 0
+    # free-energy gravity (Sec. 2.2): p_g = grav_rho0 g (y - grav_y0), walls only
+    g: float = 0.0
+    grav_rho0: float = 0.0
+    grav_y0: float = 0.0
 
     def c_params(self) -> Params:
         p = Params()
@@ -254,8 +261,10 @@ class Config:
         p.sigma_li, p.kappa_li, p.kappa_p = self.sigma_li, self.kappa_li, self.kappa_p
         p.kappa, p.A, p.fx, p.fy, p.rho_ref = self.kappa, self.A, self.fx, self.fy, self.rho_ref
         p.tile_x, p.tile_y, p.kernel_flags = self.tile_x, self.tile_y, self.kernel_flags
+        p.tile_rounds = int(self.tile_rounds)
         p.x_split, p.ax, p.rho_ave = int(self.x_split), float(self.ax), float(self.rho_ave)
         p.ax_from_step = int(self.ax_from_step)
+        p.g, p.grav_rho0, p.grav_y0 = float(self.g), float(self.grav_rho0), float(self.grav_y0)
         return p
 
     def with_launch(self, tile_x: int, tile_y: int, kernel_flags: int) -> "Config":

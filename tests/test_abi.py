@@ -201,9 +201,42 @@ def test_walls_validation():
         lbm.workspace_bytes(dataclasses.replace(drive, ax_from_step=-1))
     with pytest.raises(lbm.LbmError):
         lbm.workspace_bytes(dataclasses.replace(drive, ax=float("inf")))
-    # walls with a force normal to them: the closure would not conserve mass
-    p = dataclasses.replace(base, fy=1e-6).c_params()
-    assert lbm.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lbm.ERR_UNSUPPORTED
+    # walls with a force normal to them: the closure carries -F/2
+    assert lbm.workspace_bytes(dataclasses.replace(base, fy=1e-6)) > 0
+
+
+def test_gravity_validation():
+    """Gravity (Sec. 2.2): free energy with walls only (p_g is not periodic),
+    finite, |g| < 1, rho_0 >= 0; single lattices only."""
+    import dataclasses
+    fe = lbm.Config(16, 8, lbm.MODEL_FE, lbm.EOS_CS, 0.25, 4.0, 1.0, 0.08, kappa=0.5,
+                    walls=True, g=1e-5, grav_rho0=0.3, grav_y0=3.5)
+    assert lbm.workspace_bytes(fe) == lbm.workspace_bytes(dataclasses.replace(fe, g=0.0))
+    n = ctypes.c_size_t()
+    for bad, status in ((dataclasses.replace(fe, walls=False), lbm.ERR_INVALID_ARG),
+                        (dataclasses.replace(fe, grav_rho0=-0.1), lbm.ERR_INVALID_ARG),
+                        (dataclasses.replace(fe, g=1.5), lbm.ERR_INVALID_ARG),
+                        (dataclasses.replace(fe, g=float("nan")), lbm.ERR_INVALID_ARG),
+                        (dataclasses.replace(fe, grav_y0=float("inf")), lbm.ERR_INVALID_ARG),
+                        (dataclasses.replace(fe, model=lbm.MODEL_P), lbm.ERR_UNSUPPORTED)):
+        p = bad.c_params()
+        assert lbm.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == status
+    arr = (lbm.Params * 1)(fe.c_params())
+    assert lbm.lib().lbm_batch_workspace_bytes(1, arr, ctypes.byref(n)) == lbm.ERR_UNSUPPORTED
+
+
+def test_launch_fields_validation():
+    """The launch shape comes from explicit lbm_params fields only:
+    tile_rounds in 0 .. 64, kernel flags only with LBM_KF_SET."""
+    import dataclasses
+    fe = lbm.Config(16, 8, lbm.MODEL_FE, lbm.EOS_CS, 0.25, 4.0, 1.0, 0.08, kappa=0.5)
+    assert lbm.workspace_bytes(dataclasses.replace(fe, tile_rounds=4)) > 0
+    assert lbm.workspace_bytes(dataclasses.replace(
+        fe, kernel_flags=lbm.KF_SET | lbm.KF_NO_XCD_REMAP)) > 0
+    for bad in (dataclasses.replace(fe, tile_rounds=-1), dataclasses.replace(fe, tile_rounds=65),
+                dataclasses.replace(fe, kernel_flags=lbm.KF_NO_XCD_REMAP)):
+        with pytest.raises(lbm.LbmError):
+            lbm.workspace_bytes(bad)
 
 
 def test_viscosity_tuning_A_validation():

@@ -123,3 +123,86 @@ def test_channel_at_tr_0_5_only_pseudopotential_stable():
             ud = th.plates_diffuse(1e-7, np.arange(cfg.ny), rho[:, 0] * 0.5 / 3)
             assert np.abs(ux[:, 0] - ud).max() / ud.max() < 0.015
     assert flags[lbm.MODEL_FE] & (lbm.FLAG_NONFINITE | lbm.FLAG_EOS_DOMAIN)
+
+
+NORMAL_CASES = [
+    # (nx, ny, tile_x, tile_y, steps, fx, fy): normal force toward either
+    # wall, with and without a tangential one, ragged strips and segments
+    (101, 50, 64, 8, 2000, 1e-6, -2e-6),
+    (101, 50, 256, 7, 2000, 0.0, 3e-6),
+    (70, 33, 0, 0, 1500, -2e-6, -1e-6),
+    (5, 4, 64, 3, 500, 0.0, -1e-5),
+]
+
+
+@pytest.mark.parametrize("model", [lbm.MODEL_FE, lbm.MODEL_P])
+@pytest.mark.parametrize("nx,ny,tx,ty,steps,fx,fy", NORMAL_CASES)
+def test_walls_with_normal_force_match_oracle(model, nx, ny, tx, ty, steps, fx, fy):
+    """Walls under a body force normal to them (Sec. 5.3 closure with
+    j_y = -F_y/2; the wall density moves by +j_y on the bottom wall and by
+    -j_y on the top one, pinned on the oracle against an independent solve
+    of the closure): node by node against the oracle."""
+    cfg, rho0 = channel_cfg(model, 0.8, nx=nx, ny=ny, fx=fx, tile_x=tx, tile_y=ty)
+    cfg.fy = fy
+    obs, rho, ux, uy = gpu_run(cfg, rho0, steps)
+    s = oracle_run(cfg, rho0, steps)
+    r_o, ux_o, uy_o = s.fields()
+    assert obs["flags"] == 0 and s.flags == 0
+    assert rel_err(rho, r_o) < FP64_RTOL
+    umax = np.abs(ux_o).max() + np.abs(uy_o).max()
+    assert np.abs(ux - ux_o).max() < 1e-8 * umax + 1e-15
+    assert np.abs(uy - uy_o).max() < 1e-8 * umax + 1e-15
+    assert abs(obs["mass"] / s.observe(0, 0)["mass"] - 1) < 1e-13
+
+
+@pytest.mark.parametrize("model", [lbm.MODEL_FE, lbm.MODEL_P])
+def test_walls_with_normal_force_fp32_shifted(model):
+    cfg, rho0 = channel_cfg(model, 0.8, tile_x=64, tile_y=8)
+    cfg.fy = -2e-6
+    cfg.precision = lbm.FP32_SHIFTED
+    steps = 2000
+    obs, rho, _, uy = gpu_run(cfg, rho0, steps)
+    r_o, _, uy_o = oracle_run(cfg, rho0, steps).fields()
+    assert obs["flags"] == 0
+    assert rel_err(rho, r_o) < fp32_tol(steps, r_o)
+    # the momentum of the vapour rows is a difference of populations stored
+    # to 2^-24 of rho_l, twenty times the vapour density (measured 2.5e-3)
+    assert np.abs(uy - uy_o).max() < 1e-2 * np.abs(uy_o).max()
+
+
+@pytest.mark.parametrize("model", [lbm.MODEL_FE, lbm.MODEL_P])
+def test_liquid_column_under_normal_force_settles_like_the_oracle(model):
+    """A 64-wide liquid column under f_y = -1e-5 rho_l settles (16000 steps):
+    the GPU field equals the oracle's 3-column run of the same x-uniform
+    problem (field-relative 1e-10), the pseudopotential column is at rest
+    (|u| < 1e-12) and the free-energy one keeps the ~1e-9 flux of its walls
+    that the oracle shows."""
+    a = 0.25
+    T = cs_T(a, 0.8)
+    rl, _, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    tau = [1.0] * 9
+    if model == lbm.MODEL_FE:
+        kw = dict(kappa=0.5)
+    else:
+        m = th.match_p_to_fe(th.CS, a, 4.0, 1.0, T, 0.5)
+        tau[4] = tau[6] = 1 / 1.99
+        kw = dict(sigma_li=m["sigma_li"], kappa_p=m["kappa_p"], kappa_li=m["kappa_li"])
+    steps, ny = 16000, 32
+    out = {}
+    for nx in (64, 3):
+        cfg = lbm.Config(nx, ny, model, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tau, fy=-1e-5 * rl,
+                         walls=True, **kw)
+        out[nx] = cfg, inputs.uniform(nx, ny, rl)
+    cfg, rho0 = out[64]
+    obs, rho, _, uy = gpu_run(cfg, rho0, steps)
+    cfg3, rho3 = out[3]
+    s = oracle_run(cfg3, rho3, steps)
+    r_o, _, uy_o = s.fields()
+    assert obs["flags"] == 0 == s.flags
+    assert np.abs(rho[:, :3] - r_o).max() < 1e-10 * rl
+    assert np.ptp(rho, axis=1).max() < 1e-13 * rl
+    if model == lbm.MODEL_P:
+        assert obs["max_u"] < 1e-12
+    else:
+        assert obs["max_u"] < 1e-8
+        assert np.abs(uy[:, 0] - uy_o[:, 0]).max() < 1e-3 * np.abs(uy_o).max() + 1e-15
