@@ -216,7 +216,30 @@ def main():
     if not args.no_vdw and args.workload != "vdw-spinodal":
         vf, vrho0, vdesc = workload("vdw-spinodal", args.n)
         vr = torch.from_numpy(vrho0).to(dev)
-        variants_vdw = {"workload": vdesc}
+        variants_vdw = {
+            "workload": vdesc,
+            "valid_run": False,
+            "reason": ("not runnable as configured: the van der Waals spinodal at Tr = 0.7 "
+                       "(p'(rho_m) = -0.43, against c_s^2 = 1/3) drives velocities to ~0.1 "
+                       "within 20 steps; on the oracle (64^2) the free-energy lattice turns "
+                       "non-finite by step 10-40 for every kappa in [0.02, 1] with tau_e "
+                       "0.75 or 1, and the pseudopotential one clamps psi (imaginary at low "
+                       "and at high density, so the EOS loses its repulsion) and leaves the "
+                       "EOS domain.  The timings below are of those runs, for per-step cost "
+                       "only; 'first_flag_step' is the first of the checks at 5, 10, 20, ... "
+                       "steps that showed a flag."),
+        }
+        for mname, model in (("P", lbm.MODEL_P), ("FE", lbm.MODEL_FE)):
+            sim = lbm.Simulation(vf(model, lbm.FP64), vr)
+            first, done = None, 0
+            for t in (5, 10, 20, 40, 80, 160, 320, 640):
+                sim.step(t - done)
+                done = t
+                if sim.observe()["flags"]:
+                    first = t
+                    break
+            sim.close()
+            variants_vdw[f"{mname}_first_flag_step"] = first
         for pname, prec in precs:
             for mname, model in (("P", lbm.MODEL_P), ("FE", lbm.MODEL_FE)):
                 secs, obs = time_variant(vf(model, prec), vr, K, W)
@@ -230,9 +253,10 @@ def main():
         torch.cuda.empty_cache()
 
     # The options of the general step kernel on the same lattice, FP64: Zou-He
-    # walls (Sec. 5.3), the droplet-collision drive (Sec. 5.4), and A != 0
-    # (Eq. 20; includes the three observation passes that form the velocity
-    # field each step).  Algorithmic bytes as for the periodic step.
+    # walls (Sec. 5.3) with a tangential and a normal force, the
+    # droplet-collision drive (Sec. 5.4), A != 0 (Eq. 20; a velocity pass of
+    # the same kernel runs before each step) and free-energy gravity
+    # (Sec. 2.2, between walls).  Algorithmic bytes as for the periodic step.
     options = None
     if not args.no_options:
         import dataclasses
@@ -241,9 +265,14 @@ def main():
         cases = []
         for mname, model in (("P", lbm.MODEL_P), ("FE", lbm.MODEL_FE)):
             base = cfg_factory(model, lbm.FP64)
-            cases.append((f"{mname}_walls", dataclasses.replace(base, walls=True, fx=1e-7)))
+            cases.append((f"{mname}_walls", dataclasses.replace(base, walls=True, fx=1e-7,
+                                                                fy=-1e-7)))
             cases.append((f"{mname}_drive", dataclasses.replace(base, ax=5e-6, x_split=args.n // 2)))
         cases.append(("FE_A", dataclasses.replace(cfg_factory(lbm.MODEL_FE, lbm.FP64), A=0.1)))
+        fe = cfg_factory(lbm.MODEL_FE, lbm.FP64)
+        cases.append(("FE_gravity", dataclasses.replace(fe, walls=True, g=1e-6,
+                                                        grav_rho0=float(rho0.mean()),
+                                                        grav_y0=(args.n - 1) / 2)))
         for name, cfg in cases:
             secs, obs = time_variant(cfg, rho0_dev, ko, min(W, 20))
             ms = secs * 1e3 / ko
