@@ -158,6 +158,10 @@ typedef struct {
 #define LBM_KF_NT_STORE 1u      /* non-temporal population stores           */
 #define LBM_KF_REGCAP 2u        /* register-capped kernel, higher occupancy */
 #define LBM_KF_PIPELINE 4u      /* software-pipelined row loop (P only)     */
+#define LBM_KF_TWO_STEP 16u     /* two time steps per launch (periodic
+                                   pseudopotential lattices, 256-column
+                                   strips): the intermediate populations stay
+                                   on chip; results are bit-identical      */
 #define LBM_KF_NO_XCD_REMAP 8u  /* keep the dispatch order of the tiles
                                    (default: a contiguous band of tiles per
                                    XCD, whose L2 the neighbours share)      */

@@ -24,7 +24,8 @@ BOUNDARY_PERIODIC, BOUNDARY_WALLS = 0, 1
 FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
 
 BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS, BATCH_DROPPED = 0, 1, 2, 3, 4
-KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE, KF_NO_XCD_REMAP = 0x80000000, 1, 2, 4, 8
+KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE, KF_NO_XCD_REMAP, KF_TWO_STEP = (
+    0x80000000, 1, 2, 4, 8, 16)
 
 EXPORTED_SYMBOLS = [
     "lbm_status_string", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe",

@@ -1,0 +1,93 @@
+"""Two pseudopotential steps per launch (temporal blocking, LBM_KF_TWO_STEP).
+
+The two-step kernel keeps the first step's populations on chip and does
+every node's arithmetic in the single-step kernel's order, so its fields
+must equal those of two single steps bit for bit (and therefore the
+oracle's to its bar): ragged strips and segments, segments of one row,
+lattices narrower than the strip (columns wrap onto themselves), an odd
+step count (the last step single), both equations of state (the van der
+Waals case raises the psi clamp flag on both paths), FP64 and FP32-shifted
+storage, and the 4096^2 throughput lattice in its launch configuration.
+"""
+import numpy as np
+import pytest
+
+from oracle import theory as th
+from paper_2403_11167_amd import inputs, lbm
+from test_gpu_parity import FP64_RTOL, cs_T, droplet_rho, oracle_run, p_cfg, rel_err, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+ONE = lbm.KF_SET | lbm.KF_NT_STORE
+TWO = lbm.KF_SET | lbm.KF_NT_STORE | lbm.KF_TWO_STEP
+
+
+def run(cfg, rho0, steps):
+    import torch
+    sim = lbm.Simulation(cfg, torch.from_numpy(np.ascontiguousarray(rho0)).to(torch_dev()))
+    sim.step(steps)
+    obs, (rho, ux, uy) = sim.observe(fields=True)
+    f = sim.populations()
+    sim.close()
+    return obs, rho.cpu().numpy(), f.cpu().numpy()
+
+
+def noisy(cfg, amp=0.03, seed=4):
+    rl, rv, _ = th.maxwell(cfg.eos, cfg.a, cfg.b, cfg.R, cfg.T)
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:cfg.ny, 0:cfg.nx]
+    r = rv + (rl - rv) * (0.5 + 0.3 * np.sin(2 * np.pi * x / max(cfg.nx, 2) + 0.2)
+                          * np.cos(2 * np.pi * y / max(cfg.ny, 2)))
+    return r * (1 + amp * rng.uniform(-1, 1, size=r.shape))
+
+
+CASES = [
+    # (nx, ny, tile_y, steps)
+    (300, 130, 0, 40), (300, 130, 7, 41), (257, 9, 1, 20), (512, 64, 64, 30),
+    (70, 66, 16, 24), (5, 7, 3, 12), (256, 1, 0, 10),
+]
+
+
+@pytest.mark.parametrize("prec", [lbm.FP64, lbm.FP32_SHIFTED])
+@pytest.mark.parametrize("nx,ny,ty,steps", CASES)
+def test_two_step_equals_two_single_steps(nx, ny, ty, steps, prec):
+    cfg = p_cfg(nx, ny, a=0.25, Tr=0.75, tau=[1.0, 0.8, 1.3, 1.0, 0.7, 1.0, 0.7, 1.1, 1.1],
+                sigma_li=0.12, kappa_p=0.7, kappa_li=0.3, precision=prec)
+    rho0 = noisy(cfg)
+    o1, r1, f1 = run(cfg.with_launch(256, ty, ONE), rho0, steps)
+    o2, r2, f2 = run(cfg.with_launch(256, ty, TWO), rho0, steps)
+    assert o1["flags"] == o2["flags"] == 0
+    assert np.array_equal(f1, f2), float(np.abs(f1 - f2).max())
+    assert np.array_equal(r1, r2)
+    if prec == lbm.FP64 and nx * ny <= 40000:
+        ref = oracle_run(cfg, rho0, steps).fields()[0]
+        assert rel_err(r2, ref) < FP64_RTOL
+
+
+def test_two_step_vdw_clamp_flag():
+    """van der Waals Tr = 0.8 flat interface (psi clamped in the vapour):
+    the same flags and fields on both paths."""
+    a, b, R, T = 9 / 49, 2 / 21, 1.0, 0.8 * 4 / 7
+    rl, rv, _ = th.maxwell(th.VDW, a, b, R, T)
+    rho0 = inputs.planar_slab(256, 4, rl, rv, width=5.0, noise=1e-6, seed=1)
+    cfg = lbm.Config(256, 4, lbm.MODEL_P, lbm.EOS_VDW, a, b, R, T)
+    o1, r1, f1 = run(cfg.with_launch(256, 0, ONE), rho0, 200)
+    o2, r2, f2 = run(cfg.with_launch(256, 0, TWO), rho0, 200)
+    assert o1["flags"] == o2["flags"] == lbm.FLAG_PSI_CLAMP
+    assert np.array_equal(f1, f2)
+
+
+@pytest.mark.parametrize("prec", [lbm.FP64, lbm.FP32_SHIFTED])
+def test_two_step_throughput_lattice(prec):
+    """4096^2 spinodal (C-S a = 0.25, Tr = 0.85), the benchmark's workload:
+    the two-step path equals the single-step one after 6 steps."""
+    E, a, b, R = lbm.EOS_CS, 0.25, 4.0, 1.0
+    T = cs_T(a, 0.85)
+    rl, rv, _ = th.maxwell(E, a, b, R, T)
+    rho0 = inputs.spinodal(4096, 4096, 0.5 * (rl + rv), 0.01, seed=3)
+    cfg = lbm.Config(4096, 4096, lbm.MODEL_P, E, a, b, R, T, precision=prec)
+    o1, r1, f1 = run(cfg.with_launch(256, 0, ONE | lbm.KF_PIPELINE), rho0, 6)
+    o2, r2, f2 = run(cfg.with_launch(256, 0, TWO), rho0, 6)
+    assert o1["flags"] == o2["flags"]
+    assert np.array_equal(r1, r2)
+    assert np.array_equal(f1, f2)
