@@ -45,29 +45,46 @@ def droplet_batch(Tr, radii, precision=lbm.FP64, a=0.25):
     return meta, obs, st, m["fe"]["gamma"], T
 
 
-@pytest.mark.parametrize("Tr", [0.8, 0.7])
+# per-temperature bars on dp R_e / gamma (each radius), on the fitted slope
+# and on its intercept (relative to the largest dp)
+LAPLACE_BARS = {0.9: (0.02, 0.03, 0.02), 0.8: (0.03, 0.04, 0.02), 0.7: (0.03, 0.04, 0.02),
+                0.6: (0.05, 0.06, 0.04)}
+
+
+@pytest.mark.parametrize("Tr", [0.9, 0.8, 0.7, 0.6])
 def test_laplace_law_on_256_droplets(Tr):
     """Sec. 5.2 / Fig. 3: dp against 1/R for R in {20, 30, 40, 60} on 256^2
     lattices is a line through the origin whose slope is the planar theory's
     surface tension (App. B Eq. 15 with Eq. 26 for FE; Eq. 46 for P, whose
-    kappa^Li is matched to that value).  Bar: dp R_e within 3 % of gamma for
-    every radius and the fitted slope within 4 %: curvature corrections of
-    order W / R reach ~2-3 % at Tr = 0.8, where the smallest droplet
-    evaporates to R_e ~ 16 against a width W ~ 6 (at Tr = 0.7 everything is
-    within 1 %); intercept below 2 % of dp at the smallest radius."""
+    kappa^Li is matched to that value), at every temperature of the grid.
+    Curvature corrections of order W / R reach ~2-3 % at Tr = 0.8, where
+    the smallest droplet evaporates to R_e ~ 16 against a width W ~ 6; at
+    Tr = 0.9 (W ~ 8.8) the R = 20 droplet is below the critical radius of
+    the box and evaporates completely (checked: no droplet left), and the
+    others are within 0.5 %.  At Tr = 0.6 (W ~ 4.2) the free-energy droplets
+    sit 2-4 % below the planar theory and still approach it slowly (R = 30:
+    0.961, 0.972, 0.979 after 6e4, 1.5e5, 3e5 steps), the pseudopotential
+    ones within 1.5 %."""
     radii = (20.0, 30.0, 40.0, 60.0)
+    bar_r, bar_slope, bar_icpt = LAPLACE_BARS[Tr]
     meta, obs, st, gamma, _ = droplet_batch(Tr, radii)
     for model in (lbm.MODEL_FE, lbm.MODEL_P):
         idx = [i for i, (m, _) in enumerate(meta) if m == model]
         assert all(st[i] in (lbm.BATCH_CONVERGED, lbm.BATCH_MAXSTEPS) for i in idx)
+        for i in idx:
+            assert obs[i]["flags"] == 0
+        if Tr == 0.9:
+            small = [i for i in idx if meta[i][1] == 20.0]
+            for i in small:  # evaporated: uniform vapour, no pressure jump
+                assert abs(obs[i]["dp"]) < 0.01 * gamma / 20.0
+            idx = [i for i in idx if i not in small]
         x = np.array([1.0 / obs[i]["r_equimolar"] for i in idx])
         y = np.array([obs[i]["dp"] for i in idx])
         for i in idx:
-            assert obs[i]["flags"] == 0
-            assert abs(obs[i]["dp"] * obs[i]["r_equimolar"] / gamma - 1) < 0.03, (model, meta[i])
+            assert abs(obs[i]["dp"] * obs[i]["r_equimolar"] / gamma - 1) < bar_r, (model, meta[i])
         slope, icpt = np.polyfit(x, y, 1)
-        assert abs(slope / gamma - 1) < 0.04, model
-        assert abs(icpt) < 0.02 * y.max()
+        assert abs(slope / gamma - 1) < bar_slope, model
+        assert abs(icpt) < bar_icpt * y.max()
 
 
 def test_free_energy_droplet_is_thermodynamically_consistent():
