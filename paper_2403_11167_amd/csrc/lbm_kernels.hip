@@ -41,6 +41,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_math.h"
 
 namespace lbmk {
 
@@ -86,9 +87,11 @@ template <class C>
 __device__ __forceinline__ C d_sqrt(C v) {
   if constexpr (sizeof(C) == 4) return sqrtf(v); else return sqrt(v);
 }
+// Logarithms of the chemical potential: the reduced-range atanh series of
+// lbm_math.h (a few ulps, a third of the library functions' instructions).
 template <class C>
 __device__ __forceinline__ C d_log(C v) {
-  if constexpr (sizeof(C) == 4) return logf(v); else return log(v);
+  if constexpr (sizeof(C) == 4) return logf(v); else return lbmm::ln_f64(v);
 }
 
 // Reciprocal in the compute type.  FP32 (shifted storage) takes the
@@ -145,7 +148,7 @@ __device__ __forceinline__ C eos_mu(C rho, const KParams<C>& kp) {
 
 template <class C>
 __device__ __forceinline__ C d_log1p(C v) {
-  if constexpr (sizeof(C) == 4) return log1pf(v); else return log1p(v);
+  if constexpr (sizeof(C) == 4) return lbmm::ln1p_f32(v); else return log1p(v);
 }
 
 // Chemical potential up to a constant, from the density deviation
