@@ -12,8 +12,10 @@ leaves the EOS domain within ~50 steps on both models; its lines carry the
 non-finite flags and its free-energy timing is inflated by the special-value
 paths of log on non-finite data.  One
 step = one update of each model's lattice.  Inputs are resident in HBM
-before the timed region; the timed region is K back-to-back launches per
-model bracketed by events recorded on the library's stream.
+before the timed region; the timed region is K back-to-back steps per model
+(two per launch where the two-step kernels apply: periodic lattices at
+least 256 wide, both models) bracketed by events recorded on the library's
+stream.
 
 Prints one JSON line (metric, value in MLUPS, roofline of the dominant
 kernel, CPU oracle baseline on the host cores).
@@ -74,7 +76,8 @@ def workload(name: str, n: int):
 
 
 def time_variant(cfg, rho0_dev, steps: int, warmup: int):
-    """(seconds for `steps` launches on the library's stream, final obs)."""
+    """(seconds for `steps` steps on the library's stream, final obs, the
+    launch shape that carried them)."""
     import torch
     from paper_2403_11167_amd import lbm
     sim = lbm.Simulation(cfg, rho0_dev)
@@ -88,10 +91,11 @@ def time_variant(cfg, rho0_dev, steps: int, warmup: int):
     torch.cuda.synchronize()
     seconds = start.elapsed_time(stop) / 1e3
     obs = sim.observe(cfg.nx // 2, cfg.ny // 2)
+    info = sim.launch_info()
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return seconds, obs
+    return seconds, obs, info
 
 
 def cpu_baseline(cfg_factory, rho0, target_seconds: float):
@@ -202,12 +206,14 @@ def main():
     precs = [("fp64", lbm.FP64)] + ([] if args.no_fp32 else [("fp32_shifted", lbm.FP32_SHIFTED)])
     for pname, prec in precs:
         for mname, model in (("P", lbm.MODEL_P), ("FE", lbm.MODEL_FE)):
-            secs, obs = time_variant(cfg_factory(model, prec), rho0_dev, K, W)
+            secs, obs, info = time_variant(cfg_factory(model, prec), rho0_dev, K, W)
             es = 8 if prec == lbm.FP64 else 4
             ms = secs * 1e3 / K
             variants[f"{mname}_{pname}"] = dict(
                 mlups=N * K / secs / 1e6, ms_per_step=ms,
                 hbm_gbs_algorithmic=18 * es * N / (ms * 1e-3) / 1e9,
+                steps_per_launch=info["steps_per_launch"], strip=info["strip"],
+                segment=info["segment"],
                 flags=int(obs["flags"]), finite=bool(math.isfinite(obs["mass"])))
             print(f"# {mname} {pname}: {ms:.4f} ms/step, {N * K / secs / 1e6:.0f} MLUPS, "
                   f"flags {obs['flags']}", file=sys.stderr, flush=True)
@@ -242,7 +248,7 @@ def main():
             variants_vdw[f"{mname}_first_flag_step"] = first
         for pname, prec in precs:
             for mname, model in (("P", lbm.MODEL_P), ("FE", lbm.MODEL_FE)):
-                secs, obs = time_variant(vf(model, prec), vr, K, W)
+                secs, obs, _ = time_variant(vf(model, prec), vr, K, W)
                 ms = secs * 1e3 / K
                 variants_vdw[f"{mname}_{pname}"] = dict(
                     mlups=N * K / secs / 1e6, ms_per_step=ms, flags=int(obs["flags"]),
@@ -274,7 +280,7 @@ def main():
                                                         grav_rho0=float(rho0.mean()),
                                                         grav_y0=(args.n - 1) / 2)))
         for name, cfg in cases:
-            secs, obs = time_variant(cfg, rho0_dev, ko, min(W, 20))
+            secs, obs, _ = time_variant(cfg, rho0_dev, ko, min(W, 20))
             ms = secs * 1e3 / ko
             gbs = 18 * 8 * N / (ms * 1e-3) / 1e9
             options[name] = dict(mlups=N * ko / secs / 1e6, ms_per_step=ms,
@@ -299,15 +305,20 @@ def main():
     ms_per_step = t_p + t_fe
     value = 2 * N / (ms_per_step * 1e-3) / 1e6
 
+    # the dominant kernel: the slower model's FP64 step kernel.  One launch
+    # advances steps_per_launch time steps; its algorithmic bytes are those
+    # of that many node-updates (9 population reads + 9 writes each, FP64),
+    # its duration that many times the measured time per step
     dom = "P_fp64" if t_p >= t_fe else "FE_fp64"
-    dom_ms = max(t_p, t_fe)
-    algo_bytes = 18 * 8 * N  # 9 population reads + 9 writes, FP64
-    achieved = algo_bytes / (dom_ms * 1e-3) / 1e9
+    spl = variants[dom]["steps_per_launch"]
+    launch_ms = spl * max(t_p, t_fe)
+    algo_bytes = spl * 18 * 8 * N
+    achieved = algo_bytes / (launch_ms * 1e-3) / 1e9
     traffic, kname = load_traffic(dom)
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                    kernel=kname or dom, variant=dom, algorithmic_bytes_per_launch=algo_bytes,
-                    launch_ms=dom_ms)
+                    kernel=kname or dom, variant=dom, steps_per_launch=spl,
+                    algorithmic_bytes_per_launch=algo_bytes, launch_ms=launch_ms)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -127,8 +127,9 @@ typedef struct {
   int32_t kernel_flags; /* 0, or LBM_KF_SET | any of the LBM_KF_* below
                            (with walls: ignored, non-temporal stores only) */
   int32_t tile_rounds;  /* with tile_y = 0: the rounds of resident
-                           workgroups the tiles fill, 0 .. 64 (0: 3 for the
-                           pseudopotential, 1 for the free energy)          */
+                           workgroups the tiles fill, 0 .. 64 (0: 1 for the
+                           two-step and free-energy kernels, 3 for the
+                           single-step pseudopotential one)                 */
   /* Droplet-collision drive (Sec. 5.4): an x force a(x) |rho - rho_ave|
      added to fx, with a = +ax for x <= x_split and -ax beyond, in the steps
      that start at t >= ax_from_step (the paper: a_x = 5e-6, x_split = 100 on
@@ -159,9 +160,13 @@ typedef struct {
 #define LBM_KF_REGCAP 2u        /* register-capped kernel, higher occupancy */
 #define LBM_KF_PIPELINE 4u      /* software-pipelined row loop (P only)     */
 #define LBM_KF_TWO_STEP 16u     /* two time steps per launch (periodic
-                                   pseudopotential lattices, 256-column
-                                   strips): the intermediate populations stay
-                                   on chip; results are bit-identical      */
+                                   lattices at least 256 wide, both models):
+                                   the intermediate populations stay on
+                                   chip; results are bit-identical to two
+                                   single steps                            */
+#define LBM_KF_STRIP128 32u     /* the free-energy two-step kernel on
+                                   128-column strips (default in FP64;
+                                   256 otherwise)                          */
 #define LBM_KF_NO_XCD_REMAP 8u  /* keep the dispatch order of the tiles
                                    (default: a contiguous band of tiles per
                                    XCD, whose L2 the neighbours share)      */
@@ -221,8 +226,26 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const double* d_f);
 /* Free the host context (device memory stays with the caller). */
 lbm_status lbm_destroy(lbm_ctx* ctx);
 
+/* The launch shape that carries a run (not part of the paper's method; it
+ * lets a caller relate measured kernel times to the work of one launch). */
+typedef struct {
+  int32_t steps_per_launch; /* 2 where two steps run per launch, else 1     */
+  int32_t strip;            /* columns per workgroup strip of that kernel    */
+  int32_t segment;          /* rows per segment; 0 until the first lbm_step
+                               has fixed an automatic height                 */
+  int32_t workgroups;       /* workgroups per launch (0 before that step)    */
+  int32_t threads;          /* threads per workgroup                         */
+  int32_t reserved[3];
+} lbm_launch;
+
+/* Fill *out for ctx.  Host only, no synchronisation.  LBM_ERR_INVALID_ARG
+ * for NULL arguments. */
+lbm_status lbm_launch_info(const lbm_ctx* ctx, lbm_launch* out);
+
 /* Time the step kernel for p (its lattice size, model, EOS and precision)
- * over a list of launch shapes and kernel variants, `steps` steps each, on
+ * over a list of launch shapes and kernel variants (strip width, segment
+ * height, store kind, register cap, pipelined row loop, one or two steps
+ * per launch and the two-step kernel's strip width), `steps` steps each, on
  * a scratch state started from d_rho0, and return the fastest in
  * best->tile_x / tile_y / kernel_flags (the other fields are copied from p).
  * Uses d_workspace (lbm_workspace_bytes(p)); synchronises the stream; the

@@ -43,6 +43,12 @@
 #include "lbm.h"
 #include "lbm_math.h"
 
+// Multiply-adds are fused only within one expression, never across
+// statements: the fused kernels (two steps per launch) must round exactly
+// as the single-step kernels do, and cross-statement fusion depends on the
+// surrounding code.
+#pragma clang fp contract(on)
+
 namespace lbmk {
 
 enum { EOS_VDW = 0, EOS_CS = 1 };
@@ -1039,6 +1045,187 @@ __device__ __forceinline__ void tile_p2(const S* __restrict__ src, S* __restrict
   commit_flags(fl, flags, &s_flag);
 }
 
+// Two free-energy steps on one tile of a periodic lattice in one pass
+// (temporal blocking): the populations after the first step, g*1, never go
+// to HBM.  The workgroup has BX + 64 threads.  Lanes 0 .. BX-1 own the
+// tile's columns x0 + t for both steps; the last wavefront (the halo
+// wavefront) owns the first step's columns around the strip.  The second
+// step's density is needed two columns beyond the strip (its chemical
+// potential one column beyond), so the first step collides three halo
+// columns each side, needs the chemical potential on four and the density
+// on five: halo lane h has the column x0-1-h/2 (h even) or x0+w+h/2 (h odd),
+// and h < 10 / 8 / 6 / 4 / 2 form the first step's density / chemical
+// potential / collision and the second step's density / chemical
+// potential.
+//
+// One iteration k advances six stages, each on its own row, in three
+// phases separated by barriers (r = the first-step row fetched at k):
+//   phase 0: A(r)   pull row r, its density into the rho1 ring;
+//            D(r-3) deposit g*1 of row r-3 into the second step's pulled
+//                   populations (f_4, f_7, f_8 complete row r-4, whose
+//                   density goes into the rho2 ring);
+//   phase 1: B(r-1) chemical potential of row r-1 into the mu1 ring;
+//            E(r-5) chemical potential of the second step, row r-5;
+//   phase 2: C(r-2) pull row r-2 again (its populations were not kept),
+//                   collide it (first step), the x-moving populations into
+//                   LDS for the neighbours' deposits;
+//            F(r-6) collide row r-6 (second step) and store it.
+// Each stage reads only what earlier phases wrote, and four-row rings cover
+// the rows that a phase reads while another writes.  Between the deposit
+// and the collision, the second step keeps three complete rows of pulled
+// populations and two partial ones in registers; the first step keeps
+// none: its row is pulled twice, two iterations apart, the second time from
+// L2.  Every node does the single-step kernel's arithmetic in the same
+// order and the first step's output is rounded to the storage type, so two
+// steps of this kernel equal two single steps bit for bit.
+template <int EOS, class S, class C, int BX, int NT>
+__device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restrict__ dst,
+                                         const KParams<C>& kp, unsigned* __restrict__ flags,
+                                         int x0, int y0) {
+  __shared__ C rho1[4][BX + 10];  // columns x0-5 .. x0+w+4 (index off + 5)
+  __shared__ C mu1[4][BX + 8];    // x0-4 .. x0+w+3 (off + 4)
+  __shared__ C xb[6][BX + 6];     // x-moving g*1 of one row, x0-3 .. x0+w+2 (off + 3)
+  __shared__ C rho2[4][BX + 4];   // x0-2 .. x0+w+1 (off + 2)
+  __shared__ C mu2[4][BX + 2];    // x0-1 .. x0+w (off + 1)
+  __shared__ unsigned s_flag;
+  if (threadIdx.x == 0) s_flag = 0u;
+  const int nx = kp.nx, ny = kp.ny;
+  const int w = min(BX, nx - x0);
+  const int ly = min(kp.LY, ny - y0);
+  const int t = threadIdx.x;
+  const bool mainl = t < BX;
+  const int h = t - BX;
+  const int off = mainl ? t : ((h & 1) ? w + (h >> 1) : -1 - (h >> 1));
+  const bool own = mainl && t < w;
+  const bool dA = own || (!mainl && h < 10);
+  const bool dB = own || (!mainl && h < 8);
+  const bool dC = own || (!mainl && h < 6);
+  const bool dD = own || (!mainl && h < 4);
+  const bool dE = own || (!mainl && h < 2);
+  const int x = wrapi(x0 + (dA ? off : 0), nx);
+  const int xm = (x == 0) ? nx - 1 : x - 1;
+  const int xp = (x == nx - 1) ? 0 : x + 1;
+  const int cm = colo(xm), c0 = colo(x), cp = colo(xp);
+
+  unsigned fl = 0;
+  // second step: complete pulled rows R0 (collided at this iteration), R1,
+  // R2 (completed at this iteration); partial rows: p1 = row r-4 before the
+  // deposit (f0 f1 f3 f2 f5 f6), p2 = row r-3 (f2 f5 f6)
+  C R0[9], R1[9], R2[9];
+  C p1_0 = C(0), p1_1 = C(0), p1_3 = C(0), p1_2 = C(0), p1_5 = C(0), p1_6 = C(0);
+  C p2_2 = C(0), p2_5 = C(0), p2_6 = C(0);
+  C k0 = C(0), k2 = C(0), k4 = C(0);  // g*1 of the own column kept from C to D
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R0[i] = R1[i] = R2[i] = C(0);
+
+  auto rowoff = [&](int y) { return wrapi(y, ny) * kp.rowpitch; };
+  auto pull = [&](int y, C g[9]) {
+    const int r0 = rowoff(y), rm = rowoff(y - 1), rp = rowoff(y + 1);
+    pull9<S, C, NT>(src, rm, r0, rp, cm, c0, cp, g);
+  };
+  auto mu_at = [&](const C* bot, const C* mid, const C* top, int j) {
+    C v[9];
+    gather(bot, mid, top, j, v);
+    return mu_dev<EOS>(v[0], kp) - kp.kappa * lap9(v);
+  };
+
+  const int ra = y0 - 5;  // first-step row fetched at k = 0
+  const int niter = ly + 11;
+  for (int k = 0; k < niter; ++k) {
+    const int r = ra + k;
+    // ---- phase 0: A(r), D(r-3)
+    if (r <= y0 + ly + 4 && dA) {
+      C g[9];
+      pull(r, g);
+      const C dr = sum9(g);
+      if (own) fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dr, kp);
+      rho1[r & 3][off + 5] = dr;
+    }
+    if (r - 3 >= y0 - 3 && r - 3 <= y0 + ly + 2 && dD) {
+      const int j = off + 3;
+      // f_4(x, r-4) = g*1_4(x, r-3), f_7 from x+1, f_8 from x-1
+      R2[0] = p1_0; R2[1] = p1_1; R2[2] = p1_2; R2[3] = p1_3;
+      R2[4] = k4; R2[5] = p1_5; R2[6] = p1_6;
+      R2[7] = xb[5][j + 1];
+      R2[8] = xb[2][j - 1];
+      if (r - 4 >= y0 - 2) {
+        const C dq = sum9(R2);
+        if (own) fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dq, kp);
+        rho2[(r - 4) & 3][off + 2] = dq;
+      }
+      // row r-3: f_0 own, f_1 from x-1, f_3 from x+1 (f_2 f_5 f_6 already in)
+      p1_0 = k0; p1_1 = xb[0][j - 1]; p1_3 = xb[3][j + 1];
+      p1_2 = p2_2; p1_5 = p2_5; p1_6 = p2_6;
+      // row r-2: f_2 own, f_5 from x-1, f_6 from x+1
+      p2_2 = k2; p2_5 = xb[1][j - 1]; p2_6 = xb[4][j + 1];
+    }
+    __syncthreads();
+    // ---- phase 1: B(r-1), E(r-5)
+    if (r - 1 >= y0 - 4 && r - 1 <= y0 + ly + 3 && dB)
+      mu1[(r - 1) & 3][off + 4] = mu_at(rho1[(r - 2) & 3], rho1[(r - 1) & 3], rho1[r & 3], off + 5);
+    if (r - 5 >= y0 - 1 && r - 5 <= y0 + ly && dE)
+      mu2[(r - 5) & 3][off + 1] = mu_at(rho2[(r - 6) & 3], rho2[(r - 5) & 3], rho2[(r - 4) & 3], off + 2);
+    __syncthreads();
+    // ---- phase 2: C(r-2), F(r-6)
+    const int c = r - 2;
+    if (c >= y0 - 3 && c <= y0 + ly + 2 && dC) {
+      C g[9];
+      pull(c, g);
+      const C d0 = sum9(g);
+      C v[9], m[9];
+      gather(rho1[(c - 1) & 3], rho1[c & 3], rho1[(c + 1) & 3], off + 5, v);
+      gather(mu1[(c - 1) & 3], mu1[c & 3], mu1[(c + 1) & 3], off + 4, m);
+      C grx, gry, gmx, gmy;
+      grad_sum(v, grx, gry);
+      grad_sum(m, gmx, gmy);
+      const C rho = kp.rho_ref + d0;
+      const C Fx = -rho * gmx + kp.fx;
+      const C Fy = -rho * gmy + kp.fy;
+      C ux, uy;
+      collide<MODEL_FE>(g, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
+      // the single-step kernel stores the first step's output and loads it
+      // back: round to the storage type the same way
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = (C)(S)g[i];
+      const int j = off + 3;
+      xb[0][j] = g[1];
+      xb[1][j] = g[5];
+      xb[2][j] = g[8];
+      xb[3][j] = g[3];
+      xb[4][j] = g[6];
+      xb[5][j] = g[7];
+      k0 = g[0];
+      k2 = g[2];
+      k4 = g[4];
+    }
+    const int b = r - 6;
+    if (b >= y0 && own) {
+      C v[9], m[9];
+      gather(rho2[(b - 1) & 3], rho2[b & 3], rho2[(b + 1) & 3], off + 2, v);
+      gather(mu2[(b - 1) & 3], mu2[b & 3], mu2[(b + 1) & 3], off + 1, m);
+      C grx, gry, gmx, gmy;
+      grad_sum(v, grx, gry);
+      grad_sum(m, gmx, gmy);
+      const C d0 = sum9(R0);
+      const C rho = kp.rho_ref + d0;
+      const C Fx = -rho * gmx + kp.fx;
+      const C Fy = -rho * gmy + kp.fy;
+      C ux, uy;
+      collide<MODEL_FE>(R0, d0, rho, Fx, Fy, grx, gry, C(0), C(0), kp, ux, uy);
+      const int o = b * kp.rowpitch + c0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) st<NT>(&dst[o + 64 * i], (S)R0[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      R0[i] = R1[i];
+      R1[i] = R2[i];
+    }
+  }
+  commit_flags(fl, flags, &s_flag);
+}
+
 // Free-energy step on one tile.  GEN as for tile_p; GEN = 3 adds the A term
 // of Eq. 20 (kp.A, with the velocity field in kp.uax / kp.uay).  GEN = 2 is
 // the velocity pass that the A term needs: the same pull, stencils, force
@@ -1384,6 +1571,16 @@ __global__ __launch_bounds__(BX + 64) void k_step2_p(const S* __restrict__ src,
   tile_p2<EOS, S, C, BX, NT, sizeof(S) == 8 ? 1 : 0>(src, dst, kp, flags,
                                                    (tile % kp.nstrips) * BX,
                                                    (tile / kp.nstrips) * kp.LY);
+}
+
+// Two free-energy steps per launch (tile_fe2): BX + 64 threads.
+template <int EOS, class S, class C, int BX, int NT>
+__global__ __launch_bounds__(BX + 64) void k_step2_fe(const S* __restrict__ src,
+                                                      S* __restrict__ dst, const KParams<C> kp,
+                                                      unsigned* __restrict__ flags) {
+  const int tile = tile_index(kp.xcd_remap);
+  tile_fe2<EOS, S, C, BX, NT>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
+                              (tile / kp.nstrips) * kp.LY);
 }
 
 template <int EOS, class S, class C, int BX, int NT, int WPE, int GEN = 0>
@@ -1904,6 +2101,7 @@ struct LaunchCfg {
   int wpe;   // 1: register-capped kernel variant
   int pipe;  // 1: pipelined row loop (pseudopotential)
   int two;   // 1: two steps per launch where the model and options allow
+  int bx2;   // strip width of the two-step kernel: 128 or 256
   int auto_ly;  // 1: segment height set at the first launch from occupancy
 };
 
@@ -1921,6 +2119,7 @@ struct lbm_ctx {
   double rho_ave;  // mean initial density (collision drive)
   LaunchCfg lc;
   int nstrips, nseg, xcd_remap;
+  int nstrips2, nseg2, xcd_remap2;  // tiling of the two-step kernel (bx2 strips)
   KParams<double> kd;
   KParams<float> kf;
   // lbm_step replays runs of kGraphSteps steps as HIP graphs, captured on a
@@ -1952,17 +2151,22 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     lc.wpe = (kf & LBM_KF_REGCAP) ? 1 : 0;
     lc.pipe = (kf & LBM_KF_PIPELINE) ? 1 : 0;
     lc.two = (kf & LBM_KF_TWO_STEP) ? 1 : 0;
+    lc.bx2 = (kf & LBM_KF_STRIP128) ? 128 : 256;
   } else {
     lc.nt = 1;
     lc.wpe = p->model == LBM_MODEL_P ? 0 : 1;
     // pipelined row loop: pseudopotential always; free energy in FP32 only
     // (in FP64 its four live population rows cost a wave of occupancy)
     lc.pipe = (p->model == LBM_MODEL_P || !fp64) ? 1 : 0;
-    // two steps per launch for the pseudopotential model (256-column
-    // strips): 0.330 vs 0.476 ms (FP64) and 0.159 vs 0.233 ms (FP32) per
-    // step on 4096^2
-    lc.two = p->model == LBM_MODEL_P ? 1 : 0;
+    // two steps per launch, measured per step on 4096^2: pseudopotential
+    // (256-column strips) 0.326 vs 0.476 ms in FP64 and 0.151 vs 0.233 ms in
+    // FP32; free energy (128-column strips) 0.408 vs 0.486 ms in FP64 and
+    // 0.220 vs 0.249 ms in FP32
+    lc.two = 1;
+    lc.bx2 = p->model == LBM_MODEL_FE ? 128 : 256;
   }
+  // the pseudopotential two-step kernel runs 256-column strips only
+  if (p->model == LBM_MODEL_P) lc.bx2 = 256;
   if (p->boundary == LBM_BOUNDARY_WALLS || p->ax != 0.0 || p->A != 0.0) {
     // walls, the collision drive and A != 0 run in the general kernel:
     // plain row loop, non-temporal stores
@@ -2009,6 +2213,10 @@ void apply_launch(lbm_ctx* c) {
     k->LY = c->lc.ly;
     k->xcd_remap = c->xcd_remap;
   }
+  c->nstrips2 = (c->p.nx + c->lc.bx2 - 1) / c->lc.bx2;
+  c->nseg2 = c->nseg;
+  const int ntiles2 = c->nstrips2 * c->nseg2;
+  c->xcd_remap2 = (ntiles2 >= 64 && ntiles2 % 8 == 0 && !no_remap) ? 1 : 0;
   c->kf.nstrips = c->nstrips;
   c->kf.nseg = c->nseg;
   c->kf.LY = c->lc.ly;
@@ -2023,7 +2231,7 @@ void apply_launch(lbm_ctx* c) {
 bool two_step_ok(const lbm_ctx* c);
 
 template <class K>
-void tune_ly(lbm_ctx* c, K kernel, int bx) {
+void tune_ly(lbm_ctx* c, K kernel, int bx, int nstrips) {
   c->lc.auto_ly = 0;
   int blocks = 0, dev = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, bx, 0) != hipSuccess ||
@@ -2033,14 +2241,12 @@ void tune_ly(lbm_ctx* c, K kernel, int bx) {
     (void)hipGetLastError();
     return;  // keep the fallback height
   }
-  // measured on 4096^2: the free-energy kernel is fastest with one round,
-  // the pseudopotential kernel with about three
-  // measured on 4096^2: the free-energy kernel and the two-step kernel are
+  // measured on 4096^2: the free-energy kernel and the two-step kernels are
   // fastest with one round, the single-step pseudopotential one with three
   const int rounds = c->p.tile_rounds > 0 ? c->p.tile_rounds
                      : (c->p.model == LBM_MODEL_P && !two_step_ok(c) ? 3 : 1);
   const int resident = blocks * cus * std::max(1, rounds);
-  const int segs = std::max(1, resident / c->nstrips);
+  const int segs = std::max(1, resident / nstrips);
   int LY = (c->p.ny + segs - 1) / segs;
   LY = std::max(LY, std::min(16, c->p.ny));
   c->lc.ly = std::min(LY, c->p.ny);
@@ -2052,11 +2258,11 @@ void launch_step_w(lbm_ctx* c, const KParams<C>& kp) {
   // compile-time model branches: each model instantiates only its own kernels
   if (c->lc.auto_ly) {
     if constexpr (MODEL == MODEL_P) {
-      if (c->lc.pipe) tune_ly(c, k_step_p_pipe<EOS, S, C, BX, NT, WPE>, BX);
-      else tune_ly(c, k_step_p<EOS, S, C, BX, NT, WPE>, BX);
+      if (c->lc.pipe) tune_ly(c, k_step_p_pipe<EOS, S, C, BX, NT, WPE>, BX, c->nstrips);
+      else tune_ly(c, k_step_p<EOS, S, C, BX, NT, WPE>, BX, c->nstrips);
     } else {
-      if (c->lc.pipe) tune_ly(c, k_step_fe_pipe<EOS, S, C, BX, NT, WPE>, BX);
-      else tune_ly(c, k_step_fe<EOS, S, C, BX, NT, WPE>, BX);
+      if (c->lc.pipe) tune_ly(c, k_step_fe_pipe<EOS, S, C, BX, NT, WPE>, BX, c->nstrips);
+      else tune_ly(c, k_step_fe<EOS, S, C, BX, NT, WPE>, BX, c->nstrips);
     }
   }
   const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
@@ -2094,9 +2300,9 @@ void launch_step_gen(lbm_ctx* c, const KParams<C>& kp) {
   constexpr int WG = (MODEL == MODEL_FE) ? wpe_target<MODEL_FE, S>() : 0;
   const bool with_a = MODEL == MODEL_FE && c->p.A != 0.0;
   if (c->lc.auto_ly) {
-    if constexpr (MODEL == MODEL_P) tune_ly(c, k_step_p<EOS, S, C, BX, 1, 0, 1>, BX);
-    else if (with_a) tune_ly(c, k_step_fe<EOS, S, C, BX, 1, WG, 3>, BX);
-    else tune_ly(c, k_step_fe<EOS, S, C, BX, 1, WG, 1>, BX);
+    if constexpr (MODEL == MODEL_P) tune_ly(c, k_step_p<EOS, S, C, BX, 1, 0, 1>, BX, c->nstrips);
+    else if (with_a) tune_ly(c, k_step_fe<EOS, S, C, BX, 1, WG, 3>, BX, c->nstrips);
+    else tune_ly(c, k_step_fe<EOS, S, C, BX, 1, WG, 1>, BX, c->nstrips);
   }
   const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
   S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
@@ -2143,14 +2349,28 @@ void launch_step(lbm_ctx* c, const KParams<C>& kp) {
   else launch_step_bx<MODEL, EOS, S, C, 256>(c, kp);
 }
 
-// Two steps in one launch (pseudopotential, periodic, 256-column strips).
-// The segment height is chosen for this kernel even when a single step is
-// launched first (odd step counts), since it carries the run.
+// Two steps in one launch (periodic lattices): strips of bx2 columns
+// (256, or 128 for the free-energy kernel, whose register budget leaves two
+// 256-column workgroups per CU but four 128-column ones).  The segment
+// height is chosen for this kernel even when a single step is launched
+// first (odd step counts), since it carries the run.
+template <int EOS, class S, class C, int BX>
+void tune_two_bx(lbm_ctx* c) {
+  if (c->p.model == LBM_MODEL_P) {
+    if constexpr (BX == 256) {
+      if (c->lc.nt) tune_ly(c, k_step2_p<EOS, S, C, BX, 1>, BX + 64, c->nstrips2);
+      else tune_ly(c, k_step2_p<EOS, S, C, BX, 0>, BX + 64, c->nstrips2);
+    }
+  } else {
+    if (c->lc.nt) tune_ly(c, k_step2_fe<EOS, S, C, BX, 1>, BX + 64, c->nstrips2);
+    else tune_ly(c, k_step2_fe<EOS, S, C, BX, 0>, BX + 64, c->nstrips2);
+  }
+}
+
 template <int EOS, class S, class C>
 void tune_two(lbm_ctx* c) {
-  constexpr int BX = 256;
-  if (c->lc.nt) tune_ly(c, k_step2_p<EOS, S, C, BX, 1>, BX + 64);
-  else tune_ly(c, k_step2_p<EOS, S, C, BX, 0>, BX + 64);
+  if (c->lc.bx2 == 128) tune_two_bx<EOS, S, C, 128>(c);
+  else tune_two_bx<EOS, S, C, 256>(c);
 }
 
 void tune_two_dispatch(lbm_ctx* c) {
@@ -2164,33 +2384,51 @@ void tune_two_dispatch(lbm_ctx* c) {
   }
 }
 
-template <int EOS, class S, class C>
-void launch_step2_p(lbm_ctx* c, const KParams<C>& kp) {
-  constexpr int BX = 256;
-  if (c->lc.auto_ly) tune_two<EOS, S, C>(c);
+template <int EOS, class S, class C, int BX>
+void launch_step2_bx(lbm_ctx* c, const KParams<C>& kp_in) {
+  KParams<C> kp = kp_in;  // the two-step kernel's own tiling
+  kp.nstrips = c->nstrips2;
+  kp.nseg = c->nseg2;
+  kp.xcd_remap = c->xcd_remap2;
   const S* src = (const S*)(c->ws + (c->cur ? c->L.fB : c->L.fA));
   S* dst = (S*)(c->ws + (c->cur ? c->L.fA : c->L.fB));
   unsigned* flags = (unsigned*)(c->ws + c->L.flags);
-  dim3 grid(c->nstrips * c->nseg), block(BX + 64);
-  if (c->lc.nt)
-    hipLaunchKernelGGL((k_step2_p<EOS, S, C, BX, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
-  else
-    hipLaunchKernelGGL((k_step2_p<EOS, S, C, BX, 0>), grid, block, 0, c->stream, src, dst, kp, flags);
+  dim3 grid(c->nstrips2 * c->nseg2), block(BX + 64);
+  if (c->p.model == LBM_MODEL_P) {
+    if constexpr (BX == 256) {
+      if (c->lc.nt)
+        hipLaunchKernelGGL((k_step2_p<EOS, S, C, BX, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
+      else
+        hipLaunchKernelGGL((k_step2_p<EOS, S, C, BX, 0>), grid, block, 0, c->stream, src, dst, kp, flags);
+    }
+  } else {
+    if (c->lc.nt)
+      hipLaunchKernelGGL((k_step2_fe<EOS, S, C, BX, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
+    else
+      hipLaunchKernelGGL((k_step2_fe<EOS, S, C, BX, 0>), grid, block, 0, c->stream, src, dst, kp, flags);
+  }
   c->cur ^= 1;
 }
 
+template <int EOS, class S, class C>
+void launch_step2(lbm_ctx* c, const KParams<C>& kp) {
+  if (c->lc.auto_ly) tune_two<EOS, S, C>(c);
+  if (c->lc.bx2 == 128) launch_step2_bx<EOS, S, C, 128>(c, kp);
+  else launch_step2_bx<EOS, S, C, 256>(c, kp);
+}
+
 bool two_step_ok(const lbm_ctx* c) {
-  return c->lc.two && c->p.model == LBM_MODEL_P && !needs_gen(c->p) && c->lc.bx == 256;
+  return c->lc.two && !needs_gen(c->p) && c->lc.bx == 256;
 }
 
 void step_twice(lbm_ctx* c) {
   const bool cs = c->p.eos == LBM_EOS_CS;
   if (c->p.precision == LBM_FP64) {
-    if (cs) launch_step2_p<EOS_CS, double, double>(c, c->kd);
-    else launch_step2_p<EOS_VDW, double, double>(c, c->kd);
+    if (cs) launch_step2<EOS_CS, double, double>(c, c->kd);
+    else launch_step2<EOS_VDW, double, double>(c, c->kd);
   } else {
-    if (cs) launch_step2_p<EOS_CS, float, float>(c, c->kf);
-    else launch_step2_p<EOS_VDW, float, float>(c, c->kf);
+    if (cs) launch_step2<EOS_CS, float, float>(c, c->kf);
+    else launch_step2<EOS_VDW, float, float>(c, c->kf);
   }
 }
 
@@ -2541,6 +2779,20 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   return LBM_OK;
 }
 
+lbm_status lbm_launch_info(const lbm_ctx* c, lbm_launch* out) {
+  if (!c || !out) return LBM_ERR_INVALID_ARG;
+  memset(out, 0, sizeof(*out));
+  const bool two = two_step_ok(c);
+  out->steps_per_launch = two ? 2 : 1;
+  out->strip = two ? c->lc.bx2 : c->lc.bx;
+  out->threads = two ? c->lc.bx2 + 64 : c->lc.bx;
+  if (!c->lc.auto_ly) {
+    out->segment = c->lc.ly;
+    out->workgroups = two ? c->nstrips2 * c->nseg2 : c->nstrips * c->nseg;
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
                         const double* d_rho0, void* hip_stream, int32_t steps,
                         lbm_params* best, double* best_ms_per_step) {
@@ -2564,6 +2816,11 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
     kfs.push_back(LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_PIPELINE);
     kfs.push_back(LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_REGCAP | LBM_KF_PIPELINE);
   }
+  // two steps per launch (applies to periodic lattices with 256-column
+  // strips; elsewhere these candidates run single steps)
+  kfs.push_back(LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_TWO_STEP);
+  if (p->model == LBM_MODEL_FE)
+    kfs.push_back(LBM_KF_SET | LBM_KF_NT_STORE | LBM_KF_TWO_STEP | LBM_KF_STRIP128);
   (void)fp64;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBM_ERR_HIP;
@@ -2580,9 +2837,9 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
         q.kernel_flags = (int32_t)kf;
         lbm_ctx* c = nullptr;
         if ((st = ctx_setup(&q, d_workspace, d_rho0, h, stream, &c)) != LBM_OK) break;
-        step_once(c);  // warm-up (and first-touch of the second buffer)
+        advance(c, 2);  // warm-up (and first-touch of the second buffer)
         hipEventRecord(e0, stream);
-        for (int k = 0; k < steps; ++k) step_once(c);
+        advance(c, steps);
         hipEventRecord(e1, stream);
         if (hipEventSynchronize(e1) != hipSuccess) st = LBM_ERR_HIP;
         float ms = 0.f;

@@ -24,12 +24,13 @@ BOUNDARY_PERIODIC, BOUNDARY_WALLS = 0, 1
 FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
 
 BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS, BATCH_DROPPED = 0, 1, 2, 3, 4
-KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE, KF_NO_XCD_REMAP, KF_TWO_STEP = (
-    0x80000000, 1, 2, 4, 8, 16)
+KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE, KF_NO_XCD_REMAP, KF_TWO_STEP, KF_STRIP128 = (
+    0x80000000, 1, 2, 4, 8, 16, 32)
 
 EXPORTED_SYMBOLS = [
     "lbm_status_string", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe",
-    "lbm_get_populations", "lbm_set_populations", "lbm_destroy", "lbm_autotune",
+    "lbm_get_populations", "lbm_set_populations", "lbm_destroy", "lbm_launch_info",
+    "lbm_autotune",
     "lbm_eos_eval", "lbm_eos_critical", "lbm_maxwell", "lbm_sigma_li_theory", "lbm_fe_planar_theory",
     "lbm_match_p_to_fe",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_state",
@@ -99,6 +100,15 @@ class Obs(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class Launch(ctypes.Structure):
+    _fields_ = [("steps_per_launch", ctypes.c_int32), ("strip", ctypes.c_int32),
+                ("segment", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _lib = None
 
 
@@ -146,6 +156,7 @@ def lib():
         NP = ctypes.POINTER(MlpNorm)
         i32, f32 = ctypes.c_int32, ctypes.c_float
         L.lbm_mlp_forward.argtypes = [vp, NP, vp, i32, vp, i32, vp]
+        L.lbm_launch_info.argtypes = [vp, ctypes.POINTER(Launch)]
         L.lbm_mlp_workspace_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         L.lbm_mlp_grad.argtypes = [vp, NP, vp, vp, i32, vp, i32, vp, vp, i32, vp, sz, vp]
         L.lbm_mlp_grad_noalloc.argtypes = [vp, NP, vp, vp, i32, vp, i32, vp, vp, i32, vp]
@@ -325,6 +336,12 @@ class Simulation:
         if fields:
             return d, (rho, ux, uy)
         return d
+
+    def launch_info(self) -> dict:
+        """The launch shape carrying the run (see lbm_launch_info)."""
+        out = Launch()
+        _check(lib().lbm_launch_info(self._ctx, ctypes.byref(out)), "lbm_launch_info")
+        return out.as_dict()
 
     def populations(self):
         import torch

@@ -1,6 +1,6 @@
-"""Two pseudopotential steps per launch (temporal blocking, LBM_KF_TWO_STEP).
+"""Two steps per launch (temporal blocking, LBM_KF_TWO_STEP), both models.
 
-The two-step kernel keeps the first step's populations on chip and does
+The two-step kernels keep the first step's populations on chip and do
 every node's arithmetic in the single-step kernel's order, so its fields
 must equal those of two single steps bit for bit (and therefore the
 oracle's to its bar): ragged strips and segments, segments of one row,
@@ -14,7 +14,7 @@ import pytest
 
 from oracle import theory as th
 from paper_2403_11167_amd import inputs, lbm
-from test_gpu_parity import FP64_RTOL, cs_T, droplet_rho, oracle_run, p_cfg, rel_err, torch_dev
+from test_gpu_parity import FP64_RTOL, cs_T, fe_cfg, oracle_run, p_cfg, rel_err, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -88,6 +88,84 @@ def test_two_step_throughput_lattice(prec):
     cfg = lbm.Config(4096, 4096, lbm.MODEL_P, E, a, b, R, T, precision=prec)
     o1, r1, f1 = run(cfg.with_launch(256, 0, ONE | lbm.KF_PIPELINE), rho0, 6)
     o2, r2, f2 = run(cfg.with_launch(256, 0, TWO), rho0, 6)
+    assert o1["flags"] == o2["flags"]
+    assert np.array_equal(r1, r2)
+    assert np.array_equal(f1, f2)
+
+
+# ---------------------------------------------------------------- free energy
+FE_TAU = [1.0, 0.75, 1.2, 1.0, 0.8, 1.0, 0.8, 0.9, 0.9]
+
+
+@pytest.mark.parametrize("strip", [256, 128])
+@pytest.mark.parametrize("prec", [lbm.FP64, lbm.FP32_SHIFTED])
+@pytest.mark.parametrize("nx,ny,ty,steps", CASES)
+def test_fe_two_step_equals_two_single_steps(nx, ny, ty, steps, prec, strip):
+    """Free energy (C-S a = 0.25, Tr = 0.75, kappa = 0.5, every tau
+    different), both strip widths of the two-step kernel: ragged strips and
+    segments, one-row segments, lattices narrower than the strip (the first
+    step's five halo columns wrap onto the strip itself), odd step counts."""
+    cfg = fe_cfg(nx, ny, a=0.25, Tr=0.75, tau=FE_TAU, precision=prec)
+    rho0 = noisy(cfg)
+    two = TWO | (lbm.KF_STRIP128 if strip == 128 else 0)
+    o1, r1, f1 = run(cfg.with_launch(256, ty, ONE), rho0, steps)
+    o2, r2, f2 = run(cfg.with_launch(256, ty, two), rho0, steps)
+    assert o1["flags"] == o2["flags"] == 0
+    assert np.array_equal(f1, f2), float(np.abs(f1 - f2).max())
+    assert np.array_equal(r1, r2)
+    if prec == lbm.FP64 and nx * ny <= 40000:
+        ref = oracle_run(cfg, rho0, steps).fields()[0]
+        assert rel_err(r2, ref) < FP64_RTOL
+
+
+def test_fe_two_step_vdw_and_body_force():
+    """van der Waals EOS with a constant body force (both enter the
+    periodic kernel): the same fields and flags on both paths."""
+    cfg = fe_cfg(300, 40, a=9 / 49, Tr=0.85, eos=lbm.EOS_VDW, kappa=0.02, fx=1e-6, fy=-2e-6,
+                 tau=FE_TAU)
+    rho0 = noisy(cfg, amp=0.01)
+    o1, r1, f1 = run(cfg.with_launch(256, 0, ONE), rho0, 30)
+    o2, r2, f2 = run(cfg.with_launch(256, 0, TWO), rho0, 30)
+    assert o1["flags"] == o2["flags"]
+    assert np.array_equal(f1, f2, equal_nan=True)
+
+
+def test_fe_two_step_domain_flags():
+    """A density past the EOS domain (C-S b rho / 4 >= 1, put into the
+    populations after the start) and a NaN elsewhere are flagged by both
+    paths, with the same flags."""
+    import torch
+    cfg = fe_cfg(260, 20, a=0.25, Tr=0.75, tau=FE_TAU)
+    rho0 = noisy(cfg)
+    flags = []
+    for kf in (ONE, TWO):
+        sim = lbm.Simulation(cfg.with_launch(256, 0, kf), torch.from_numpy(rho0).to(torch_dev()))
+        f = sim.populations()
+        f[0, 7, 100] += 1.2  # b rho / 4 > 1 at (100, 7)
+        f[0, 15, 250] = float("nan")
+        sim.set_populations(f.contiguous())
+        sim.step(2)
+        flags.append(sim.observe()["flags"])
+        sim.close()
+    assert flags[0] & lbm.FLAG_EOS_DOMAIN and flags[0] & lbm.FLAG_NONFINITE
+    assert flags[0] == flags[1]
+
+
+@pytest.mark.parametrize("strip", [256, 128])
+@pytest.mark.parametrize("prec", [lbm.FP64, lbm.FP32_SHIFTED])
+def test_fe_two_step_throughput_lattice(prec, strip):
+    """4096^2 spinodal (C-S a = 0.25, Tr = 0.85, kappa = 0.5, tau_e = 0.75),
+    the benchmark's free-energy workload: equal to the single-step path."""
+    E, a, b, R = lbm.EOS_CS, 0.25, 4.0, 1.0
+    T = cs_T(a, 0.85)
+    rl, rv, _ = th.maxwell(E, a, b, R, T)
+    rho0 = inputs.spinodal(4096, 4096, 0.5 * (rl + rv), 0.01, seed=3)
+    tau = [1.0] * 9
+    tau[1] = 0.75
+    cfg = lbm.Config(4096, 4096, lbm.MODEL_FE, E, a, b, R, T, tau=tau, kappa=0.5, precision=prec)
+    two = TWO | (lbm.KF_STRIP128 if strip == 128 else 0)
+    o1, r1, f1 = run(cfg.with_launch(256, 0, ONE), rho0, 6)
+    o2, r2, f2 = run(cfg.with_launch(256, 0, two), rho0, 6)
     assert o1["flags"] == o2["flags"]
     assert np.array_equal(r1, r2)
     assert np.array_equal(f1, f2)
