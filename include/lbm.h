@@ -165,8 +165,8 @@ typedef struct {
                                    chip; results are bit-identical to two
                                    single steps                            */
 #define LBM_KF_STRIP128 32u     /* the free-energy two-step kernel on
-                                   128-column strips (default in FP64;
-                                   256 otherwise)                          */
+                                   128-column strips (the default)         */
+#define LBM_KF_STRIP192 64u     /* ... on 192-column strips                */
 #define LBM_KF_NO_XCD_REMAP 8u  /* keep the dispatch order of the tiles
                                    (default: a contiguous band of tiles per
                                    XCD, whose L2 the neighbours share)      */
@@ -305,6 +305,14 @@ lbm_status lbm_batch_set_limit(lbm_batch* b, int32_t i, int64_t max_steps);
  * already has a different partner gives LBM_ERR_INVALID_ARG.  Host-only; no
  * device work. */
 lbm_status lbm_batch_set_partner(lbm_batch* b, int32_t i, int32_t j);
+
+/* Measurement of the runs so far (not part of the paper's method): node
+ * updates issued (lattice nodes of the active problems times the steps of
+ * each chunk), GPU time between events recorded on the stream around each
+ * chunk's graph launch, and the number of chunks.  Each pointer may be
+ * NULL.  Host only. */
+lbm_status lbm_batch_stats(const lbm_batch* b, int64_t* node_updates, double* gpu_ms,
+                           int64_t* chunks);
 
 /* Per-problem state (LBM_BATCH_*), steps taken, last measured max |du| and
  * sticky flags; each pointer may be NULL, else points to n elements. */

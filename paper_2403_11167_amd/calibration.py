@@ -146,17 +146,29 @@ def _shape(size):
     return int(size), int(size), int(size)
 
 
-def build_problems(tuples, sizes, precision, guesses=None):
+def with_tile(cfg: lbm.Config, tiles) -> lbm.Config:
+    """cfg with the batch tile shape of its size class (model, nx, ny) from
+    `tiles` (autotune_batch_tiles), if listed there."""
+    if not tiles:
+        return cfg
+    tx_ty = tiles.get((cfg.model, cfg.nx, cfg.ny))
+    if tx_ty is None:
+        return cfg
+    return cfg.with_launch(int(tx_ty[0]), int(tx_ty[1]), 0)
+
+
+def build_problems(tuples, sizes, precision, guesses=None, tiles=None):
     """Configs and initial fields for one flat and one droplet lattice per
     tuple.  sizes: per tuple an int L (flat and droplet L x L) or a triple
     (flat nx, flat ny, droplet L).  guesses: per-tuple (rho_l, rho_v, W)
-    (None: plain guesses)."""
+    (None: plain guesses).  tiles: batch tile shape per size class (see
+    autotune_batch_tiles)."""
     cfgs, rho0s, meta = [], [], []
     for k, (t, size) in enumerate(zip(tuples, sizes)):
         g = guesses[k] if guesses is not None else initial_guess(t)
         rl, rv, W = g[:3]
         fx, fy, L = _shape(size)
-        cfgs.append(model_config(t, fx, fy, precision))
+        cfgs.append(with_tile(model_config(t, fx, fy, precision), tiles))
         rho0s.append(flat_rho0(fx, fy, rl, rv, W))
         meta.append((k, "flat"))
         cd = model_config(t, L, L, precision)
@@ -168,10 +180,53 @@ def build_problems(tuples, sizes, precision, guesses=None):
                 dl, dv = rl, rv
             if not (0 < dv < dl):
                 dl, dv = rl, rv
-        cfgs.append(cd)
+        cfgs.append(with_tile(cd, tiles))
         rho0s.append(droplet_rho0(L, dl, dv, W))
         meta.append((k, "droplet"))
     return cfgs, rho0s, meta
+
+
+TILE_CANDIDATES = ((64, 8), (64, 16), (64, 32), (64, 64), (256, 8), (256, 16), (256, 32),
+                   (256, 64))
+
+
+def autotune_batch_tiles(precision=lbm.FP32_SHIFTED, sizes=SIZES, steps=40, nodes=1 << 20,
+                         log=None):
+    """The batch tile shape (tile_x, tile_y) of each size class (model, L x L)
+    of the calibration: for every class, a batch of flat-interface lattices
+    of that class (about `nodes` nodes in all, mid-range tuple Tr = 0.75,
+    w = 5, kappa = 1.25) runs `steps` lockstep steps per candidate shape,
+    timed by the batch's own GPU clock (lbm_batch_stats); the least GPU time
+    per node update wins.  Strips of 256 columns are tried where L >= 256.
+    Returns {(model, L, L): (tile_x, tile_y)} and the timings."""
+    import torch
+    say = log or (lambda *a: None)
+    dev = torch.device("cuda:0")
+    best, table = {}, []
+    for model in (lbm.MODEL_P, lbm.MODEL_FE):
+        t = Tuple4(model, 0.75, 5.0, 1.25)
+        rl, rv, W = initial_guess(t)
+        for L in sizes:
+            n = max(2, nodes // (L * L))
+            rho = torch.from_numpy(flat_rho0(L, L, rl, rv, W)).to(dev)
+            timings = []
+            for tx, ty in TILE_CANDIDATES:
+                if (tx == 256 and L < 256) or ty > L:
+                    continue
+                cfg = model_config(t, L, L, precision).with_launch(tx, ty, 0)
+                b = lbm.Batch([cfg] * n, [rho] * n)
+                b.run(check_every=steps // 2, du_tol=0.0, max_steps=steps)
+                st = b.stats()
+                b.close()
+                timings.append((st["gpu_ms"] * 1e6 / max(st["node_updates"], 1), tx, ty))
+            ns, tx, ty = min(timings)
+            best[(model, L, L)] = (tx, ty)
+            table.append(dict(model="P" if model == lbm.MODEL_P else "FE", L=L, lattices=n,
+                              tile_x=tx, tile_y=ty, ns_per_node_update=ns,
+                              candidates={f"{a}x{c}": v for v, a, c in timings}))
+            say(f"batch tiles: {'P' if model == lbm.MODEL_P else 'FE'} L={L}: {tx}x{ty}, "
+                f"{ns:.4f} ns per node update")
+    return best, table
 
 
 def pair_units(batch, meta):
@@ -186,8 +241,23 @@ def pair_units(batch, meta):
             first[k] = i
 
 
+def batch_measurement(batch, run_seconds: float, precision: int) -> dict:
+    """GPU share and algorithmic bandwidth of a batch's runs: node updates
+    times the 9 population reads and 9 writes of one update, over the GPU
+    time of its chunks (events around each graph launch); gpu_busy is that
+    GPU time over the wall time of the run calls."""
+    st = batch.stats()
+    es = 8 if precision == lbm.FP64 else 4
+    sec = st["gpu_ms"] * 1e-3
+    gbs = 18 * es * st["node_updates"] / sec / 1e9 if sec > 0 else math.nan
+    return dict(node_updates=st["node_updates"], gpu_s=sec, chunks=st["chunks"],
+                run_s=run_seconds, gpu_busy=sec / run_seconds if run_seconds > 0 else math.nan,
+                hbm_gbs_algorithmic=gbs, frac_of_8tbs=gbs / 8000.0,
+                bytes_per_node_update=18 * es)
+
+
 def run_calibration(tuples, sizes, precision=lbm.FP32_SHIFTED, guesses=None,
-                    check_every=200, du_tol=1e-9, max_steps=200000):
+                    check_every=200, du_tol=1e-9, max_steps=200000, tiles=None):
     """Run the flat + droplet pair of every tuple to equilibrium in one batch.
     Returns (labels, info): labels[k] = dict(rho_l, rho_v, W, sigma, ok) and
     info = dict(seconds, steps, states, steps_per_problem, ...).  The timed
@@ -197,19 +267,22 @@ def run_calibration(tuples, sizes, precision=lbm.FP32_SHIFTED, guesses=None,
 
     import torch
     dev = torch.device("cuda:0")
-    cfgs, rho0s, meta = build_problems(tuples, sizes, precision, guesses)
+    cfgs, rho0s, meta = build_problems(tuples, sizes, precision, guesses, tiles)
     t0 = time.perf_counter()
     batch = lbm.Batch(cfgs, [torch.from_numpy(r).to(dev) for r in rho0s])
     pair_units(batch, meta)
+    tr = time.perf_counter()
     steps = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps)
+    run_s = time.perf_counter() - tr
     labels = measure(batch, cfgs, meta, len(tuples))
     seconds = time.perf_counter() - t0
     states, nsteps, du, flags = batch.state()
+    meas = batch_measurement(batch, run_s, precision)
     batch.close()
     units = sum(1 for lab in labels if lab["ok"])
     info = dict(seconds=seconds, steps=steps, states=states, steps_per_problem=nsteps,
                 problems=len(cfgs), converged_units=units,
-                units_per_second=units / seconds if seconds > 0 else math.nan)
+                units_per_second=units / seconds if seconds > 0 else math.nan, batch=meas)
     return labels, info
 
 
@@ -277,7 +350,8 @@ def lattice_agrees(kind, m, p, rtol_rho=0.01, rtol_sigma=0.03, rtol_w=0.05) -> b
 
 def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
                            check_every=200, du_tol=1e-9, max_steps=200000,
-                           crossings=8.0, rtol_rho=0.01, rtol_sigma=0.03, rtol_w=0.05):
+                           crossings=8.0, rtol_rho=0.01, rtol_sigma=0.03, rtol_w=0.05,
+                           tiles=None):
     """Calibration with the surrogate in front of the method.
 
     1. The surrogate predicts (rho_l, rho_v, sigma, W) for every tuple and
@@ -306,13 +380,15 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
     t0 = time.perf_counter()
     pred = surrogate.predict(features(tuples))
     cfgs, rho0s, meta = build_problems(tuples, sizes, precision,
-                                       seeded_guesses(pred, tuples=tuples))
+                                       seeded_guesses(pred, tuples=tuples), tiles)
     batch = lbm.Batch(cfgs, [torch.from_numpy(r).to(dev) for r in rho0s])
     pair_units(batch, meta)
     for i, c in enumerate(cfgs):
         v = crossings * max(c.nx, c.ny) / CS_LATTICE
         batch.set_limit(i, int(math.ceil(v / check_every)) * check_every)
+    tr = time.perf_counter()
     steps = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps)
+    run_s = time.perf_counter() - tr
     states = batch.state()[0]
     lat = [None] * len(cfgs)
     accepted = [False] * len(cfgs)
@@ -332,7 +408,9 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
     # verification steps included
     for i in resume:
         batch.set_limit(i, max_steps)
+    tr = time.perf_counter()
     steps2 = batch.run(check_every=check_every, du_tol=du_tol, max_steps=max_steps) if resume else 0
+    run_s += time.perf_counter() - tr
     states, nsteps, du, flags = batch.state()
     for i in resume:
         if states[i] == lbm.BATCH_CONVERGED:
@@ -350,6 +428,7 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
         if not (lab.get("drop_contrast", 0.0) > 0.5 * (lab["rho_l"] - lab["rho_v"])):
             lab["ok"] = False
     seconds = time.perf_counter() - t0
+    meas = batch_measurement(batch, run_s, precision)
     batch.close()
     units = sum(1 for lab in labels if lab["ok"])
     n_acc = sum(1 for v in both if v == 2)
@@ -357,7 +436,7 @@ def run_seeded_calibration(tuples, sizes, surrogate, precision=lbm.FP32_SHIFTED,
                 problems=len(cfgs), converged_units=units,
                 units_per_second=units / seconds if seconds > 0 else math.nan,
                 accepted=n_acc, accepted_lattices=int(sum(accepted)),
-                fallback=len(tuples) - n_acc, prediction=pred)
+                fallback=len(tuples) - n_acc, prediction=pred, batch=meas)
     return labels, info
 
 
@@ -465,10 +544,13 @@ def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_
     t2 = time.perf_counter()
     pred_only = sur.predict(feats)
     infer_s = time.perf_counter() - t2
-    lab_p, inf_p = run_calibration(tup, sizes, max_steps=max_steps)
+    t3 = time.perf_counter()
+    tiles, tile_table = autotune_batch_tiles(log=say)
+    tune_s = time.perf_counter() - t3
+    lab_p, inf_p = run_calibration(tup, sizes, max_steps=max_steps, tiles=tiles)
     say(f"plain: {inf_p['seconds']:.1f} s, {inf_p['converged_units']} tuples")
     lab_s, inf_s = run_seeded_calibration(tup, sizes, sur, max_steps=max_steps,
-                                          crossings=crossings)
+                                          crossings=crossings, tiles=tiles)
     say(f"seeded: {inf_s['seconds']:.1f} s, {inf_s['converged_units']} tuples, "
         f"{inf_s['accepted']} accepted after verification")
     rel, m = compare(lab_p, lab_s)
@@ -485,13 +567,18 @@ def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_
                       size=list(train_size), generation_s=gen_s, train_s=train_s,
                       epochs=epochs, loss_first=float(losses[0]), loss_last=float(losses[-1])),
         plain=dict(seconds=inf_p["seconds"], tuples_converged=inf_p["converged_units"],
-                   tuples_per_s=inf_p["units_per_second"], lockstep_steps=inf_p["steps"]),
+                   tuples_per_s=inf_p["units_per_second"], lockstep_steps=inf_p["steps"],
+                   batch=inf_p["batch"]),
         seeded=dict(seconds=inf_s["seconds"], tuples_converged=inf_s["converged_units"],
                     tuples_per_s=inf_s["units_per_second"], lockstep_steps=inf_s["steps"],
                     accepted_after_verification=inf_s["accepted"],
                     lattices_accepted_after_verification=inf_s["accepted_lattices"],
-                    fallback=inf_s["fallback"], verification_crossings=crossings),
+                    fallback=inf_s["fallback"], verification_crossings=crossings,
+                    batch=inf_s["batch"]),
         speedup=inf_p["seconds"] / inf_s["seconds"],
+        batch_tiles=dict(seconds=tune_s, classes=tile_table,
+                         note="tile shape per size class, timed on batches of that class "
+                              "before both legs (autotune_batch_tiles); not in either leg's time"),
         surrogate_only=dict(seconds=infer_s, tuples=n_held,
                             speedup_vs_plain=inf_p["seconds"] / infer_s if infer_s > 0 else None,
                             note="labels predicted directly by the trained network (BF16 "

@@ -100,6 +100,12 @@ __device__ __forceinline__ C d_log(C v) {
   if constexpr (sizeof(C) == 4) return logf(v); else return lbmm::ln_f64(v);
 }
 
+// Fused multiply-add a b + c in the compute type.
+template <class C>
+__device__ __forceinline__ C fmad(C a, C b, C c) {
+  if constexpr (sizeof(C) == 4) return __builtin_fmaf(a, b, c); else return __builtin_fma(a, b, c);
+}
+
 // Reciprocal in the compute type.  FP32 (shifted storage) takes the
 // hardware reciprocal (1 ulp) instead of the correctly rounded division
 // sequence: the FP32 step is bound by its vector ALU, and an ulp here is
@@ -409,23 +415,22 @@ __device__ __forceinline__ void collide(C g[9], C drho, C rho, C Fx, C Fy,
   // M^-1 (Eq. 49) in factored form.  The rest population is closed on the
   // mass, g*_0 = rho* - sum_{i>0} g*_i (row 0 of M is all ones), which is
   // the same number without the bias a rounded 1/9 would put on the mass.
+  // (the multiply-adds written out: each population is two fused steps)
   C r9 = drho * C(1.0 / 9.0);
   C Aax = r9 - se * C(1.0 / 36.0) - sz * C(1.0 / 18.0);
   C Adg = r9 + se * C(1.0 / 18.0) + sz * C(1.0 / 36.0);
-  C X1 = (sjx - sqx) * C(1.0 / 6.0);
-  C Y1 = (sjy - sqy) * C(1.0 / 6.0);
-  C P4 = spxx * C(0.25);
+  C dX = sjx - sqx, dY = sjy - sqy;
   C X5 = sjx * C(1.0 / 6.0) + sqx * C(1.0 / 12.0);
   C Y5 = sjy * C(1.0 / 6.0) + sqy * C(1.0 / 12.0);
-  C Q4 = spxy * C(0.25);
-  g[1] = Aax + X1 + P4;
-  g[2] = Aax + Y1 - P4;
-  g[3] = Aax - X1 + P4;
-  g[4] = Aax - Y1 - P4;
-  g[5] = Adg + X5 + Y5 + Q4;
-  g[6] = Adg - X5 + Y5 - Q4;
-  g[7] = Adg - X5 - Y5 + Q4;
-  g[8] = Adg + X5 - Y5 - Q4;
+  C Ap = Adg + X5, Am = Adg - X5;
+  g[1] = fmad(spxx, C(0.25), fmad(dX, C(1.0 / 6.0), Aax));
+  g[2] = fmad(-spxx, C(0.25), fmad(dY, C(1.0 / 6.0), Aax));
+  g[3] = fmad(spxx, C(0.25), fmad(-dX, C(1.0 / 6.0), Aax));
+  g[4] = fmad(-spxx, C(0.25), fmad(-dY, C(1.0 / 6.0), Aax));
+  g[5] = fmad(spxy, C(0.25), Ap + Y5);
+  g[6] = fmad(-spxy, C(0.25), Am + Y5);
+  g[7] = fmad(spxy, C(0.25), Am - Y5);
+  g[8] = fmad(-spxy, C(0.25), Ap - Y5);
   g[0] = drho - (((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8])));
 }
 
@@ -1078,7 +1083,12 @@ __device__ __forceinline__ void tile_p2(const S* __restrict__ src, S* __restrict
 // L2.  Every node does the single-step kernel's arithmetic in the same
 // order and the first step's output is rounded to the storage type, so two
 // steps of this kernel equal two single steps bit for bit.
-template <int EOS, class S, class C, int BX, int NT>
+// PF = 1 (software pipelining): at the start of phase 1 every lane issues
+// the second pull of row r-2 and then the pull of row r+1 for the next
+// iteration's A, unconditionally (a lane without a column reads a valid
+// one), so that the wait for row r-2 in phase 2 leaves row r+1 in flight
+// (see tile_p_pipe); it costs 18 registers per lane.
+template <int EOS, class S, class C, int BX, int NT, int PF>
 __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restrict__ dst,
                                          const KParams<C>& kp, unsigned* __restrict__ flags,
                                          int x0, int y0) {
@@ -1131,12 +1141,19 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
 
   const int ra = y0 - 5;  // first-step row fetched at k = 0
   const int niter = ly + 11;
+  C gA[9], gC[9];  // PF: row r (fetched one iteration ahead), row r-2
+  if constexpr (PF != 0) pull(ra, gA);
   for (int k = 0; k < niter; ++k) {
     const int r = ra + k;
     // ---- phase 0: A(r), D(r-3)
     if (r <= y0 + ly + 4 && dA) {
       C g[9];
-      pull(r, g);
+      if constexpr (PF != 0) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = gA[i];
+      } else {
+        pull(r, g);
+      }
       const C dr = sum9(g);
       if (own) fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dr, kp);
       rho1[r & 3][off + 5] = dr;
@@ -1161,6 +1178,10 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
     }
     __syncthreads();
     // ---- phase 1: B(r-1), E(r-5)
+    if constexpr (PF != 0) {
+      pull(r - 2, gC);
+      pull(r + 1, gA);
+    }
     if (r - 1 >= y0 - 4 && r - 1 <= y0 + ly + 3 && dB)
       mu1[(r - 1) & 3][off + 4] = mu_at(rho1[(r - 2) & 3], rho1[(r - 1) & 3], rho1[r & 3], off + 5);
     if (r - 5 >= y0 - 1 && r - 5 <= y0 + ly && dE)
@@ -1170,7 +1191,12 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
     const int c = r - 2;
     if (c >= y0 - 3 && c <= y0 + ly + 2 && dC) {
       C g[9];
-      pull(c, g);
+      if constexpr (PF != 0) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = gC[i];
+      } else {
+        pull(c, g);
+      }
       const C d0 = sum9(g);
       C v[9], m[9];
       gather(rho1[(c - 1) & 3], rho1[c & 3], rho1[(c + 1) & 3], off + 5, v);
@@ -1574,13 +1600,13 @@ __global__ __launch_bounds__(BX + 64) void k_step2_p(const S* __restrict__ src,
 }
 
 // Two free-energy steps per launch (tile_fe2): BX + 64 threads.
-template <int EOS, class S, class C, int BX, int NT>
+template <int EOS, class S, class C, int BX, int PF>
 __global__ __launch_bounds__(BX + 64) void k_step2_fe(const S* __restrict__ src,
                                                       S* __restrict__ dst, const KParams<C> kp,
                                                       unsigned* __restrict__ flags) {
   const int tile = tile_index(kp.xcd_remap);
-  tile_fe2<EOS, S, C, BX, NT>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
-                              (tile / kp.nstrips) * kp.LY);
+  tile_fe2<EOS, S, C, BX, 1, PF>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
+                                 (tile / kp.nstrips) * kp.LY);
 }
 
 template <int EOS, class S, class C, int BX, int NT, int WPE, int GEN = 0>
@@ -1613,6 +1639,11 @@ constexpr int wpe_target() {
 // One launch covers every tile of every active lattice of one (model, EOS,
 // strip width) group; the tile table names the lattice and the tile origin,
 // the lattice's descriptor its parameters, buffers, flags and check outputs.
+// The launch is persistent: at most one round of resident workgroups walks
+// the group's table with a stride of the grid, and the number of active
+// tiles is read from device memory, so the host shrinks the table when
+// lattices retire without changing the launch (or the graph that holds it).
+// Each workgroup's loop ends at that count, which no kernel changes.
 struct BatchTile {
   int inst, x0, y0, pad;
 };
@@ -1628,19 +1659,31 @@ struct InstDesc {
   unsigned long long* du;
 };
 
+// (the checking step of the pseudopotential FP32 kernel carries the
+// velocity comparison and the tile loop: one wave less, so it does not
+// spill)
+template <int MODEL, class S, int CHK>
+constexpr int batch_wpe() {
+  return wpe_target<MODEL, S>() - ((CHK && MODEL == MODEL_P && sizeof(S) == 4) ? 1 : 0);
+}
+
 template <int MODEL, int EOS, class S, class C, int BX, int NT, int CHK>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(wpe_target<MODEL, S>())))
-void k_batch_step(const BatchTile* __restrict__ tiles, const InstDesc<C>* __restrict__ inst,
-                  int parity) {
-  const BatchTile bt = tiles[blockIdx.x];
-  const InstDesc<C>* d = inst + bt.inst;
-  const S* src = (const S*)(parity ? d->fB : d->fA);
-  S* dst = (S*)(parity ? d->fA : d->fB);
-  const ChkOut<C> ck{d->uxp, d->uyp, d->du};
-  if constexpr (MODEL == MODEL_P)
-    tile_p<EOS, S, C, BX, NT, CHK>(src, dst, d->kp, d->flags, bt.x0, bt.y0, ck);
-  else
-    tile_fe<EOS, S, C, BX, NT, CHK>(src, dst, d->kp, d->flags, bt.x0, bt.y0, ck);
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(batch_wpe<MODEL, S, CHK>())))
+void k_batch_step(const BatchTile* __restrict__ tiles, const int* __restrict__ count,
+                  const InstDesc<C>* __restrict__ inst, int parity) {
+  const int n = *count;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const BatchTile bt = tiles[t];
+    const InstDesc<C>* d = inst + bt.inst;
+    const S* src = (const S*)(parity ? d->fB : d->fA);
+    S* dst = (S*)(parity ? d->fA : d->fB);
+    const ChkOut<C> ck{d->uxp, d->uyp, d->du};
+    if constexpr (MODEL == MODEL_P)
+      tile_p<EOS, S, C, BX, NT, CHK>(src, dst, d->kp, d->flags, bt.x0, bt.y0, ck);
+    else
+      tile_fe<EOS, S, C, BX, NT, CHK>(src, dst, d->kp, d->flags, bt.x0, bt.y0, ck);
+    __syncthreads();  // the next tile reuses the LDS rings
+  }
 }
 
 // ---- initial state ------------------------------------------------------------
@@ -2101,7 +2144,8 @@ struct LaunchCfg {
   int wpe;   // 1: register-capped kernel variant
   int pipe;  // 1: pipelined row loop (pseudopotential)
   int two;   // 1: two steps per launch where the model and options allow
-  int bx2;   // strip width of the two-step kernel: 128 or 256
+  int bx2;   // strip width of the two-step kernel: 128, 192 or 256
+  int pipe2; // 1: pipelined free-energy two-step kernel (FP32)
   int auto_ly;  // 1: segment height set at the first launch from occupancy
 };
 
@@ -2151,7 +2195,8 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     lc.wpe = (kf & LBM_KF_REGCAP) ? 1 : 0;
     lc.pipe = (kf & LBM_KF_PIPELINE) ? 1 : 0;
     lc.two = (kf & LBM_KF_TWO_STEP) ? 1 : 0;
-    lc.bx2 = (kf & LBM_KF_STRIP128) ? 128 : 256;
+    lc.bx2 = (kf & LBM_KF_STRIP128) ? 128 : (kf & LBM_KF_STRIP192) ? 192 : 256;
+    lc.pipe2 = (kf & LBM_KF_PIPELINE) ? 1 : 0;
   } else {
     lc.nt = 1;
     lc.wpe = p->model == LBM_MODEL_P ? 0 : 1;
@@ -2159,11 +2204,15 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     // (in FP64 its four live population rows cost a wave of occupancy)
     lc.pipe = (p->model == LBM_MODEL_P || !fp64) ? 1 : 0;
     // two steps per launch, measured per step on 4096^2: pseudopotential
-    // (256-column strips) 0.326 vs 0.476 ms in FP64 and 0.151 vs 0.233 ms in
-    // FP32; free energy (128-column strips) 0.408 vs 0.486 ms in FP64 and
-    // 0.220 vs 0.249 ms in FP32
+    // (256-column strips) 0.338 vs 0.476 ms in FP64 and 0.152 vs 0.233 ms in
+    // FP32; free energy 0.405 vs 0.486 ms in FP64 and 0.193 vs 0.249 ms in
+    // FP32
     lc.two = 1;
-    lc.bx2 = p->model == LBM_MODEL_FE ? 128 : 256;
+    // free energy: FP64 128-column strips (192: 0.406 ms, 256: 0.610);
+    // FP32 192-column strips with the pipelined row loop (0.193 ms; 128 /
+    // 256 pipelined 0.202 / 0.201, 192 plain 0.198)
+    lc.bx2 = p->model == LBM_MODEL_FE ? (fp64 ? 128 : 192) : 256;
+    lc.pipe2 = (p->model == LBM_MODEL_FE && !fp64) ? 1 : 0;
   }
   // the pseudopotential two-step kernel runs 256-column strips only
   if (p->model == LBM_MODEL_P) lc.bx2 = 256;
@@ -2362,7 +2411,7 @@ void tune_two_bx(lbm_ctx* c) {
       else tune_ly(c, k_step2_p<EOS, S, C, BX, 0>, BX + 64, c->nstrips2);
     }
   } else {
-    if (c->lc.nt) tune_ly(c, k_step2_fe<EOS, S, C, BX, 1>, BX + 64, c->nstrips2);
+    if (c->lc.pipe2) tune_ly(c, k_step2_fe<EOS, S, C, BX, sizeof(S) == 4 ? 1 : 0>, BX + 64, c->nstrips2);
     else tune_ly(c, k_step2_fe<EOS, S, C, BX, 0>, BX + 64, c->nstrips2);
   }
 }
@@ -2370,6 +2419,7 @@ void tune_two_bx(lbm_ctx* c) {
 template <int EOS, class S, class C>
 void tune_two(lbm_ctx* c) {
   if (c->lc.bx2 == 128) tune_two_bx<EOS, S, C, 128>(c);
+  else if (c->lc.bx2 == 192) tune_two_bx<EOS, S, C, 192>(c);
   else tune_two_bx<EOS, S, C, 256>(c);
 }
 
@@ -2402,8 +2452,9 @@ void launch_step2_bx(lbm_ctx* c, const KParams<C>& kp_in) {
         hipLaunchKernelGGL((k_step2_p<EOS, S, C, BX, 0>), grid, block, 0, c->stream, src, dst, kp, flags);
     }
   } else {
-    if (c->lc.nt)
-      hipLaunchKernelGGL((k_step2_fe<EOS, S, C, BX, 1>), grid, block, 0, c->stream, src, dst, kp, flags);
+    if (c->lc.pipe2)
+      hipLaunchKernelGGL((k_step2_fe<EOS, S, C, BX, sizeof(S) == 4 ? 1 : 0>), grid, block, 0, c->stream,
+                         src, dst, kp, flags);
     else
       hipLaunchKernelGGL((k_step2_fe<EOS, S, C, BX, 0>), grid, block, 0, c->stream, src, dst, kp, flags);
   }
@@ -2414,6 +2465,7 @@ template <int EOS, class S, class C>
 void launch_step2(lbm_ctx* c, const KParams<C>& kp) {
   if (c->lc.auto_ly) tune_two<EOS, S, C>(c);
   if (c->lc.bx2 == 128) launch_step2_bx<EOS, S, C, 128>(c, kp);
+  else if (c->lc.bx2 == 192) launch_step2_bx<EOS, S, C, 192>(c, kp);
   else launch_step2_bx<EOS, S, C, 256>(c, kp);
 }
 
@@ -2901,21 +2953,38 @@ struct lbm_batch {
   std::vector<BatchInst> inst;
   size_t desc_off, tiles_off, du_off, tiles_cap;
   size_t flagptr_off, flagout_off;  // per-instance flag pointers, gathered flags
+  size_t counts_off;                // active tile count of each group (device)
   int parity;  // common population parity of all instances
-  // one tile table per (model, EOS, strip width) group, all in one buffer
-  std::vector<std::pair<GroupKey, std::pair<int, int>>> groups;  // key -> (offset, count)
+  // one tile table per (model, EOS, strip width) group, all in one buffer:
+  // each group owns a fixed region sized for all its lattices, and its
+  // launch a grid set when the graph is captured; retirement changes the
+  // tables and counts, and a new graph is captured only when a group
+  // empties or its grid exceeds twice its tiles
+  struct Group {
+    GroupKey key;
+    int offset, capacity, count, grid, resident;
+  };
+  std::vector<Group> groups;
   bool tables_valid;
+  unsigned graph_groups = 0;  // groups with tiles when the graph was captured
   hipGraphExec_t graph;
   int graph_steps;
   int graph_parity;
+  // measurement: node updates issued, and GPU time between events recorded
+  // around each chunk's graph launch
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int64_t node_updates = 0;
+  double gpu_ms = 0.0;
+  int64_t chunks = 0;
 };
 
 namespace {
 
 struct BatchLayout {
   std::vector<size_t> inst_off, chk_off;
-  size_t desc_off, tiles_off, du_off, flagptr_off, flagout_off, total, tiles_cap;
+  size_t desc_off, tiles_off, du_off, flagptr_off, flagout_off, counts_off, total, tiles_cap;
 };
+constexpr int kMaxGroups = 8;  // 2 models x 2 EOS x 2 strip widths
 
 BatchLayout make_batch_layout(int n, const lbm_params* p) {
   BatchLayout B;
@@ -2943,31 +3012,53 @@ BatchLayout make_batch_layout(int n, const lbm_params* p) {
   off += align_up(n * sizeof(unsigned*));
   B.flagout_off = off;
   off += align_up(n * sizeof(unsigned));
+  B.counts_off = off;
+  off += align_up(kMaxGroups * sizeof(int));
   B.total = off;
   return B;
 }
 
+// Resident workgroups of a batch kernel on this device (occupancy x CUs).
+template <class K>
+int resident_blocks(K kernel, int bx) {
+  int blocks = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, bx, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      blocks < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return 1024;
+  }
+  return blocks * cus;
+}
+
+// chk < 0: only fix the group's grid (about one round of resident
+// workgroups, at most one per active tile), outside any capture
 template <int MODEL, int EOS, class S, class C, int BX>
-void launch_batch_group(lbm_batch* b, const BatchTile* tiles, int ntiles, int chk) {
+void launch_batch_group(lbm_batch* b, lbm_batch::Group& g, int chk) {
+  if (chk < 0) {
+    if (g.resident == 0) g.resident = resident_blocks(k_batch_step<MODEL, EOS, S, C, BX, 1, 0>, BX);
+    g.grid = std::max(1, std::min(g.count, g.resident));
+    return;
+  }
   const InstDesc<C>* desc = (const InstDesc<C>*)(b->ws + b->desc_off);
+  const BatchTile* tiles = (const BatchTile*)(b->ws + b->tiles_off) + g.offset;
+  const int* count = (const int*)(b->ws + b->counts_off) + (&g - b->groups.data());
   if (chk)
-    hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 1>), dim3(ntiles), dim3(BX), 0,
-                       b->launch, tiles, desc, b->parity);
+    hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 1>), dim3(g.grid), dim3(BX), 0,
+                       b->launch, tiles, count, desc, b->parity);
   else
-    hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 0>), dim3(ntiles), dim3(BX), 0,
-                       b->launch, tiles, desc, b->parity);
+    hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 0>), dim3(g.grid), dim3(BX), 0,
+                       b->launch, tiles, count, desc, b->parity);
 }
 
 template <class S, class C>
 void batch_step_typed(lbm_batch* b, int chk) {
-  const BatchTile* base = (const BatchTile*)(b->ws + b->tiles_off);
   for (auto& g : b->groups) {
-    const GroupKey& k = g.first;
-    const BatchTile* t = base + g.second.first;
-    int cnt = g.second.second;
-    if (cnt == 0) continue;
+    if (chk >= 0 && g.count == 0) continue;  // no launch for an empty group
+    const GroupKey& k = g.key;
 #define LBM_GROUP(M, E, X)                                                       \
-  if (k.model == M && k.eos == E && k.bx == X) launch_batch_group<M, E, S, C, X>(b, t, cnt, chk)
+  if (k.model == M && k.eos == E && k.bx == X) launch_batch_group<M, E, S, C, X>(b, g, chk)
     LBM_GROUP(MODEL_P, EOS_CS, 64);
     LBM_GROUP(MODEL_P, EOS_CS, 256);
     LBM_GROUP(MODEL_P, EOS_VDW, 64);
@@ -2978,16 +3069,18 @@ void batch_step_typed(lbm_batch* b, int chk) {
     LBM_GROUP(MODEL_FE, EOS_VDW, 256);
 #undef LBM_GROUP
   }
-  b->parity ^= 1;
+  if (chk >= 0) b->parity ^= 1;
 }
 
+// chk: 1 checking step, 0 plain step, -1 fix the launch grids only
 void batch_step(lbm_batch* b, int chk) {
   if (b->fp64) batch_step_typed<double, double>(b, chk);
   else batch_step_typed<float, float>(b, chk);
 }
 
 // Rebuild the tile tables of the active instances, largest first within
-// each group, and upload them (outside any graph capture).
+// each group, and upload them with the counts (outside any graph capture).
+// The first call fixes each group's region and grid from all lattices.
 lbm_status rebuild_tables(lbm_batch* b) {
   std::map<GroupKey, std::vector<BatchTile>> tabs;
   std::vector<int> order(b->n);
@@ -2997,6 +3090,23 @@ lbm_status rebuild_tables(lbm_batch* b) {
     const lbm_params& pc = b->inst[c].ctx->p;
     return (int64_t)pa.nx * pa.ny > (int64_t)pc.nx * pc.ny;
   });
+  if (b->groups.empty()) {
+    // first call: each group's region (and launch) is sized for the tiles of
+    // all its lattices, retired ones included, since a retired lattice may
+    // resume (lbm_batch_set_limit)
+    std::map<GroupKey, int> cap;
+    for (int i = 0; i < b->n; ++i) {
+      lbm_ctx* c = b->inst[i].ctx;
+      cap[GroupKey{c->p.model, c->p.eos, c->lc.bx}] += c->nseg * c->nstrips;
+    }
+    int off = 0;
+    for (auto& kv : cap) {
+      b->groups.push_back({kv.first, off, kv.second, 0, 0, 0});
+      off += kv.second;
+    }
+    if ((size_t)off > b->tiles_cap || b->groups.size() > (size_t)kMaxGroups)
+      return LBM_ERR_WORKSPACE;
+  }
   for (int i : order) {
     BatchInst& I = b->inst[i];
     if (I.state != LBM_BATCH_ACTIVE) continue;
@@ -3006,15 +3116,20 @@ lbm_status rebuild_tables(lbm_batch* b) {
     for (int s = 0; s < c->nseg; ++s)
       for (int x = 0; x < c->nstrips; ++x) v.push_back(BatchTile{i, x * c->lc.bx, s * c->lc.ly, 0});
   }
-  std::vector<BatchTile> all;
-  b->groups.clear();
-  for (auto& kv : tabs) {
-    b->groups.push_back({kv.first, {(int)all.size(), (int)kv.second.size()}});
-    all.insert(all.end(), kv.second.begin(), kv.second.end());
+  std::vector<BatchTile> all(b->tiles_cap);
+  std::vector<int> counts(kMaxGroups, 0);
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    auto& g = b->groups[gi];
+    auto it = tabs.find(g.key);
+    g.count = it == tabs.end() ? 0 : (int)it->second.size();
+    if (g.count > g.capacity) return LBM_ERR_WORKSPACE;  // cannot happen: sized for all
+    if (g.count) std::copy(it->second.begin(), it->second.end(), all.begin() + g.offset);
+    counts[gi] = g.count;
   }
-  if (all.size() > b->tiles_cap) return LBM_ERR_WORKSPACE;
-  if (!all.empty() &&
-      hipMemcpyAsync(b->ws + b->tiles_off, all.data(), all.size() * sizeof(BatchTile),
+  if ((!all.empty() &&
+       hipMemcpyAsync(b->ws + b->tiles_off, all.data(), all.size() * sizeof(BatchTile),
+                      hipMemcpyHostToDevice, b->stream) != hipSuccess) ||
+      hipMemcpyAsync(b->ws + b->counts_off, counts.data(), kMaxGroups * sizeof(int),
                      hipMemcpyHostToDevice, b->stream) != hipSuccess)
     return LBM_ERR_HIP;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_ERR_HIP;
@@ -3034,6 +3149,23 @@ __global__ void k_gather_flags(const unsigned* const* __restrict__ ptrs, unsigne
   if (i < n) out[i] = *ptrs[i];
 }
 
+// A launch with more than twice as many workgroups as tiles wastes its
+// dispatch on workgroups that exit at once (the tail of a run, when a few
+// slow lattices remain): then the graph is captured again with smaller
+// grids, which happens a few times per group as its lattices retire.
+bool grids_oversized(const lbm_batch* b) {
+  for (const auto& g : b->groups)
+    if (g.count > 0 && 2 * g.count < g.grid) return true;
+  return false;
+}
+
+unsigned group_mask(const lbm_batch* b) {
+  unsigned m = 0;
+  for (size_t i = 0; i < b->groups.size(); ++i)
+    if (b->groups[i].count > 0) m |= 1u << i;
+  return m;
+}
+
 void drop_graph(lbm_batch* b) {
   if (b->graph) hipGraphExecDestroy(b->graph);
   b->graph = nullptr;
@@ -3046,6 +3178,7 @@ void drop_graph(lbm_batch* b) {
 // caller's stream.  The du slots are cleared by a kernel, not a memset node.
 lbm_status capture_chunk(lbm_batch* b, int steps) {
   drop_graph(b);
+  batch_step(b, -1);  // launch grids from occupancy, before the capture
   int parity0 = b->parity;
   hipGraph_t g;
   if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -3070,6 +3203,7 @@ lbm_status capture_chunk(lbm_batch* b, int steps) {
   }
   b->graph_steps = steps;
   b->graph_parity = parity0;
+  b->graph_groups = group_mask(b);
   return LBM_OK;
 }
 
@@ -3129,12 +3263,19 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
     delete b;
     return LBM_ERR_HIP;
   }
+  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return LBM_ERR_HIP;
+  }
   b->ws = (char*)d_workspace;
   b->desc_off = B.desc_off;
   b->tiles_off = B.tiles_off;
   b->du_off = B.du_off;
   b->flagptr_off = B.flagptr_off;
   b->flagout_off = B.flagout_off;
+  b->counts_off = B.counts_off;
   b->tiles_cap = B.tiles_cap;
   b->parity = 0;
   b->tables_valid = false;
@@ -3151,6 +3292,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
   }
   if (st != LBM_OK) {
     for (auto& I : b->inst) delete I.ctx;
+    (void)hipEventDestroy(b->ev0);
+    (void)hipEventDestroy(b->ev1);
     hipStreamDestroy(b->cap_stream);
     delete b;
     return st;
@@ -3178,6 +3321,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
                      hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
     for (auto& I : b->inst) delete I.ctx;
+    (void)hipEventDestroy(b->ev0);
+    (void)hipEventDestroy(b->ev1);
     hipStreamDestroy(b->cap_stream);
     delete b;
     return LBM_ERR_HIP;
@@ -3212,15 +3357,23 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
       any |= (I.state == LBM_BATCH_ACTIVE);
     }
     if (!any) break;
+    // the graph holds fixed grids that read the tile counts from device
+    // memory: a new table needs no new graph unless a group has emptied
+    // (or refilled), which changes the launches the graph holds
     if (!b->tables_valid) {
       if ((st = rebuild_tables(b)) != LBM_OK) break;
-      drop_graph(b);
+      if (group_mask(b) != b->graph_groups || grids_oversized(b)) drop_graph(b);
     }
     int chunk = (int)std::min<int64_t>(K, max_steps - done);
     chunk = std::max(2, chunk - (chunk & 1));
     if (!b->graph || b->graph_steps != chunk || b->graph_parity != b->parity)
       if ((st = capture_chunk(b, chunk)) != LBM_OK) break;
-    if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
+    if (hipEventRecord(b->ev0, b->stream) != hipSuccess ||
+        hipGraphLaunch(b->graph, b->stream) != hipSuccess ||
+        hipEventRecord(b->ev1, b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
+    for (auto& I : b->inst)
+      if (I.state == LBM_BATCH_ACTIVE)
+        b->node_updates += (int64_t)I.ctx->p.nx * I.ctx->p.ny * chunk;
     b->parity ^= (chunk & 1);
     done += chunk;
     if (hipMemcpyAsync(du_bits.data(), b->ws + b->du_off, b->n * sizeof(unsigned long long),
@@ -3228,6 +3381,11 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
     if (hipMemcpyAsync(fl.data(), b->ws + b->flagout_off, b->n * sizeof(uint32_t),
                        hipMemcpyDeviceToHost, b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
     if (hipStreamSynchronize(b->stream) != hipSuccess) { st = LBM_ERR_HIP; break; }
+    {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, b->ev0, b->ev1) == hipSuccess) b->gpu_ms += ms;
+      b->chunks += 1;
+    }
     for (int i = 0; i < b->n; ++i) {
       BatchInst& I = b->inst[i];
       if (I.state != LBM_BATCH_ACTIVE) continue;
@@ -3337,8 +3495,19 @@ lbm_status lbm_batch_destroy(lbm_batch* b) {
   if (!b) return LBM_ERR_INVALID_ARG;
   drop_graph(b);
   for (auto& I : b->inst) delete I.ctx;
+  (void)hipEventDestroy(b->ev0);
+  (void)hipEventDestroy(b->ev1);
   hipStreamDestroy(b->cap_stream);
   delete b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_stats(const lbm_batch* b, int64_t* node_updates, double* gpu_ms,
+                           int64_t* chunks) {
+  if (!b) return LBM_ERR_INVALID_ARG;
+  if (node_updates) *node_updates = b->node_updates;
+  if (gpu_ms) *gpu_ms = b->gpu_ms;
+  if (chunks) *chunks = b->chunks;
   return LBM_OK;
 }
 

@@ -26,6 +26,7 @@ FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
 BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS, BATCH_DROPPED = 0, 1, 2, 3, 4
 KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE, KF_NO_XCD_REMAP, KF_TWO_STEP, KF_STRIP128 = (
     0x80000000, 1, 2, 4, 8, 16, 32)
+KF_STRIP192 = 64
 
 EXPORTED_SYMBOLS = [
     "lbm_status_string", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe",
@@ -35,6 +36,7 @@ EXPORTED_SYMBOLS = [
     "lbm_match_p_to_fe",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_state",
     "lbm_batch_observe", "lbm_batch_destroy", "lbm_batch_set_limit", "lbm_batch_set_partner",
+    "lbm_batch_stats",
     "lbm_mlp_forward", "lbm_mlp_workspace_bytes", "lbm_mlp_grad", "lbm_mlp_adam",
     "lbm_mlp_train_step", "lbm_mlp_grad_noalloc",
 ]
@@ -145,6 +147,8 @@ def lib():
                                        ctypes.POINTER(vp)]
         L.lbm_batch_run.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_int64)]
+        L.lbm_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.lbm_batch_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int64), D,
                                       ctypes.POINTER(ctypes.c_uint32)]
@@ -424,6 +428,14 @@ class Batch:
     def set_partner(self, i: int, j: int):
         """Problems i and j form one unit (see lbm_batch_set_partner)."""
         _check(lib().lbm_batch_set_partner(self._h, int(i), int(j)), "lbm_batch_set_partner")
+
+    def stats(self) -> dict:
+        """Node updates issued, GPU milliseconds of the chunks and chunk count
+        of all runs so far (see lbm_batch_stats)."""
+        nu, ms, ch = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().lbm_batch_stats(self._h, ctypes.byref(nu), ctypes.byref(ms),
+                                     ctypes.byref(ch)), "lbm_batch_stats")
+        return dict(node_updates=nu.value, gpu_ms=ms.value, chunks=ch.value)
 
     def state(self):
         """(state, steps, du, flags) lists."""

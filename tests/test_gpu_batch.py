@@ -220,3 +220,37 @@ def test_step_limit_retires_and_resumes():
         rref, _ = oracle_rho(c, r0, nsteps[i])
         assert rel(rho.cpu().numpy(), rref) < FP64_RTOL, i
     b.close()
+
+
+def test_persistent_tile_loop_and_stats():
+    """More tiles than resident workgroups (1024^2 lattices in 8-row
+    segments: 512 tiles each, 2048 in all), so the persistent launch walks
+    its table in several rounds: the batch equals the same lattices run one
+    by one, bit for bit, and its statistics count every node update."""
+    a = 0.25
+    T = cs_T(a, 0.8)
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    tauF = [1.0] * 9
+    tauF[1] = 0.75
+    cfgs, r0s = [], []
+    for k, model in enumerate((0, 1, 0, 1)):
+        if model == 0:
+            c = lbm.Config(1024, 1024, 0, lbm.EOS_CS, a, 4.0, 1.0, T, sigma_li=0.1, kappa_p=0.9)
+        else:
+            c = lbm.Config(1024, 1024, 1, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tauF, kappa=0.5)
+        cfgs.append(c.with_launch(256, 8, lbm.KF_SET | lbm.KF_NT_STORE))
+        r0s.append(inputs.spinodal(1024, 1024, 0.5 * (rl + rv), 0.01, seed=10 + k))
+    steps = 40
+    b = lbm.Batch(cfgs, [to_dev(r) for r in r0s])
+    b.run(check_every=20, du_tol=0.0, max_steps=steps)
+    st = b.stats()
+    assert st["node_updates"] == 4 * 1024 * 1024 * steps
+    assert st["chunks"] == 2 and st["gpu_ms"] > 0
+    for i, (c, r0) in enumerate(zip(cfgs, r0s)):
+        _, (rb, _, _) = b.observe(i, fields=True)
+        sim = lbm.Simulation(c, to_dev(r0))
+        sim.step(steps)
+        _, (rs, _, _) = sim.observe(fields=True)
+        sim.close()
+        assert np.array_equal(rb.cpu().numpy(), rs.cpu().numpy()), i
+    b.close()

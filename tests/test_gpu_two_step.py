@@ -97,17 +97,22 @@ def test_two_step_throughput_lattice(prec):
 FE_TAU = [1.0, 0.75, 1.2, 1.0, 0.8, 1.0, 0.8, 0.9, 0.9]
 
 
-@pytest.mark.parametrize("strip", [256, 128])
+# two-step kernel variants: strip width, pipelined row loop (FP32)
+FE_VARIANTS = {"256": TWO, "128": TWO | lbm.KF_STRIP128, "192": TWO | lbm.KF_STRIP192,
+               "128pipe": TWO | lbm.KF_STRIP128 | lbm.KF_PIPELINE}
+
+
+@pytest.mark.parametrize("variant", list(FE_VARIANTS))
 @pytest.mark.parametrize("prec", [lbm.FP64, lbm.FP32_SHIFTED])
 @pytest.mark.parametrize("nx,ny,ty,steps", CASES)
-def test_fe_two_step_equals_two_single_steps(nx, ny, ty, steps, prec, strip):
+def test_fe_two_step_equals_two_single_steps(nx, ny, ty, steps, prec, variant):
     """Free energy (C-S a = 0.25, Tr = 0.75, kappa = 0.5, every tau
-    different), both strip widths of the two-step kernel: ragged strips and
+    different), every variant of the two-step kernel: ragged strips and
     segments, one-row segments, lattices narrower than the strip (the first
     step's five halo columns wrap onto the strip itself), odd step counts."""
     cfg = fe_cfg(nx, ny, a=0.25, Tr=0.75, tau=FE_TAU, precision=prec)
     rho0 = noisy(cfg)
-    two = TWO | (lbm.KF_STRIP128 if strip == 128 else 0)
+    two = FE_VARIANTS[variant]
     o1, r1, f1 = run(cfg.with_launch(256, ty, ONE), rho0, steps)
     o2, r2, f2 = run(cfg.with_launch(256, ty, two), rho0, steps)
     assert o1["flags"] == o2["flags"] == 0
@@ -151,9 +156,9 @@ def test_fe_two_step_domain_flags():
     assert flags[0] == flags[1]
 
 
-@pytest.mark.parametrize("strip", [256, 128])
+@pytest.mark.parametrize("variant", list(FE_VARIANTS))
 @pytest.mark.parametrize("prec", [lbm.FP64, lbm.FP32_SHIFTED])
-def test_fe_two_step_throughput_lattice(prec, strip):
+def test_fe_two_step_throughput_lattice(prec, variant):
     """4096^2 spinodal (C-S a = 0.25, Tr = 0.85, kappa = 0.5, tau_e = 0.75),
     the benchmark's free-energy workload: equal to the single-step path."""
     E, a, b, R = lbm.EOS_CS, 0.25, 4.0, 1.0
@@ -163,7 +168,7 @@ def test_fe_two_step_throughput_lattice(prec, strip):
     tau = [1.0] * 9
     tau[1] = 0.75
     cfg = lbm.Config(4096, 4096, lbm.MODEL_FE, E, a, b, R, T, tau=tau, kappa=0.5, precision=prec)
-    two = TWO | (lbm.KF_STRIP128 if strip == 128 else 0)
+    two = FE_VARIANTS[variant]
     o1, r1, f1 = run(cfg.with_launch(256, 0, ONE), rho0, 6)
     o2, r2, f2 = run(cfg.with_launch(256, 0, two), rho0, 6)
     assert o1["flags"] == o2["flags"]
