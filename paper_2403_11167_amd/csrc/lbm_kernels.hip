@@ -1078,17 +1078,19 @@ __device__ __forceinline__ void tile_p2(const S* __restrict__ src, S* __restrict
 // Each stage reads only what earlier phases wrote, and four-row rings cover
 // the rows that a phase reads while another writes.  Between the deposit
 // and the collision, the second step keeps three complete rows of pulled
-// populations and two partial ones in registers; the first step keeps
-// none: its row is pulled twice, two iterations apart, the second time from
-// L2.  Every node does the single-step kernel's arithmetic in the same
-// order and the first step's output is rounded to the storage type, so two
-// steps of this kernel equal two single steps bit for bit.
-// PF = 1 (software pipelining): at the start of phase 1 every lane issues
-// the second pull of row r-2 and then the pull of row r+1 for the next
-// iteration's A, unconditionally (a lane without a column reads a valid
-// one), so that the wait for row r-2 in phase 2 leaves row r+1 in flight
-// (see tile_p_pipe); it costs 18 registers per lane.
-template <int EOS, class S, class C, int BX, int NT, int PF>
+// populations and two partial ones in registers.  Every node does the
+// single-step kernel's arithmetic in the same order and the first step's
+// output is rounded to the storage type, so two steps of this kernel equal
+// two single steps bit for bit.
+// The first step's row r-2 reaches the collision in one of two ways:
+//   HOLD = 0 (FP64, whose registers are spent): pulled a second time in
+//            phase 2, two iterations after A pulled it;
+//   HOLD = 1 (FP32): A's rows are kept in registers for two iterations, and
+//            the pull of row r+1 is issued in phase 1 for the next
+//            iteration's A, unconditionally (a lane without a column reads
+//            a valid one), so that it stays in flight through phase 2
+//            (see tile_p_pipe); 27 more registers per lane.
+template <int EOS, class S, class C, int BX, int NT, int HOLD>
 __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restrict__ dst,
                                          const KParams<C>& kp, unsigned* __restrict__ flags,
                                          int x0, int y0) {
@@ -1141,14 +1143,15 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
 
   const int ra = y0 - 5;  // first-step row fetched at k = 0
   const int niter = ly + 11;
-  C gA[9], gC[9];  // PF: row r (fetched one iteration ahead), row r-2
-  if constexpr (PF != 0) pull(ra, gA);
+  C gA[9];         // HOLD: row r, fetched one iteration ahead
+  C h1[9], h2[9];  // HOLD: rows r-1 and r-2 as A pulled them
+  if constexpr (HOLD) pull(ra, gA);
   for (int k = 0; k < niter; ++k) {
     const int r = ra + k;
     // ---- phase 0: A(r), D(r-3)
+    C g[9];
     if (r <= y0 + ly + 4 && dA) {
-      C g[9];
-      if constexpr (PF != 0) {
+      if constexpr (HOLD) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = gA[i];
       } else {
@@ -1178,10 +1181,7 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
     }
     __syncthreads();
     // ---- phase 1: B(r-1), E(r-5)
-    if constexpr (PF != 0) {
-      pull(r - 2, gC);
-      pull(r + 1, gA);
-    }
+    if constexpr (HOLD) pull(r + 1, gA);
     if (r - 1 >= y0 - 4 && r - 1 <= y0 + ly + 3 && dB)
       mu1[(r - 1) & 3][off + 4] = mu_at(rho1[(r - 2) & 3], rho1[(r - 1) & 3], rho1[r & 3], off + 5);
     if (r - 5 >= y0 - 1 && r - 5 <= y0 + ly && dE)
@@ -1191,9 +1191,9 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
     const int c = r - 2;
     if (c >= y0 - 3 && c <= y0 + ly + 2 && dC) {
       C g[9];
-      if constexpr (PF != 0) {
+      if constexpr (HOLD) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = gC[i];
+        for (int i = 0; i < 9; ++i) g[i] = h2[i];
       } else {
         pull(c, g);
       }
@@ -1247,6 +1247,10 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
     for (int i = 0; i < 9; ++i) {
       R0[i] = R1[i];
       R1[i] = R2[i];
+      if constexpr (HOLD) {
+        h2[i] = h1[i];
+        h1[i] = g[i];
+      }
     }
   }
   commit_flags(fl, flags, &s_flag);
@@ -1600,13 +1604,15 @@ __global__ __launch_bounds__(BX + 64) void k_step2_p(const S* __restrict__ src,
 }
 
 // Two free-energy steps per launch (tile_fe2): BX + 64 threads.
-template <int EOS, class S, class C, int BX, int PF>
+// Non-temporal stores; FP32 keeps the first step's rows (HOLD).
+template <int EOS, class S, class C, int BX>
 __global__ __launch_bounds__(BX + 64) void k_step2_fe(const S* __restrict__ src,
                                                       S* __restrict__ dst, const KParams<C> kp,
                                                       unsigned* __restrict__ flags) {
   const int tile = tile_index(kp.xcd_remap);
-  tile_fe2<EOS, S, C, BX, 1, PF>(src, dst, kp, flags, (tile % kp.nstrips) * BX,
-                                 (tile / kp.nstrips) * kp.LY);
+  tile_fe2<EOS, S, C, BX, 1, sizeof(S) == 4 ? 1 : 0>(src, dst, kp, flags,
+                                                   (tile % kp.nstrips) * BX,
+                                                   (tile / kp.nstrips) * kp.LY);
 }
 
 template <int EOS, class S, class C, int BX, int NT, int WPE, int GEN = 0>
@@ -2145,7 +2151,6 @@ struct LaunchCfg {
   int pipe;  // 1: pipelined row loop (pseudopotential)
   int two;   // 1: two steps per launch where the model and options allow
   int bx2;   // strip width of the two-step kernel: 128, 192 or 256
-  int pipe2; // 1: pipelined free-energy two-step kernel (FP32)
   int auto_ly;  // 1: segment height set at the first launch from occupancy
 };
 
@@ -2196,7 +2201,6 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     lc.pipe = (kf & LBM_KF_PIPELINE) ? 1 : 0;
     lc.two = (kf & LBM_KF_TWO_STEP) ? 1 : 0;
     lc.bx2 = (kf & LBM_KF_STRIP128) ? 128 : (kf & LBM_KF_STRIP192) ? 192 : 256;
-    lc.pipe2 = (kf & LBM_KF_PIPELINE) ? 1 : 0;
   } else {
     lc.nt = 1;
     lc.wpe = p->model == LBM_MODEL_P ? 0 : 1;
@@ -2205,14 +2209,12 @@ LaunchCfg resolve_launch(const lbm_params* p) {
     lc.pipe = (p->model == LBM_MODEL_P || !fp64) ? 1 : 0;
     // two steps per launch, measured per step on 4096^2: pseudopotential
     // (256-column strips) 0.338 vs 0.476 ms in FP64 and 0.152 vs 0.233 ms in
-    // FP32; free energy 0.405 vs 0.486 ms in FP64 and 0.193 vs 0.249 ms in
+    // FP32; free energy 0.406 vs 0.486 ms in FP64 and 0.178 vs 0.249 ms in
     // FP32
     lc.two = 1;
     // free energy: FP64 128-column strips (192: 0.406 ms, 256: 0.610);
-    // FP32 192-column strips with the pipelined row loop (0.193 ms; 128 /
-    // 256 pipelined 0.202 / 0.201, 192 plain 0.198)
+    // FP32 192-column strips (0.178 ms; 128: 0.192, 256: 0.214)
     lc.bx2 = p->model == LBM_MODEL_FE ? (fp64 ? 128 : 192) : 256;
-    lc.pipe2 = (p->model == LBM_MODEL_FE && !fp64) ? 1 : 0;
   }
   // the pseudopotential two-step kernel runs 256-column strips only
   if (p->model == LBM_MODEL_P) lc.bx2 = 256;
@@ -2411,8 +2413,7 @@ void tune_two_bx(lbm_ctx* c) {
       else tune_ly(c, k_step2_p<EOS, S, C, BX, 0>, BX + 64, c->nstrips2);
     }
   } else {
-    if (c->lc.pipe2) tune_ly(c, k_step2_fe<EOS, S, C, BX, sizeof(S) == 4 ? 1 : 0>, BX + 64, c->nstrips2);
-    else tune_ly(c, k_step2_fe<EOS, S, C, BX, 0>, BX + 64, c->nstrips2);
+    tune_ly(c, k_step2_fe<EOS, S, C, BX>, BX + 64, c->nstrips2);
   }
 }
 
@@ -2452,11 +2453,7 @@ void launch_step2_bx(lbm_ctx* c, const KParams<C>& kp_in) {
         hipLaunchKernelGGL((k_step2_p<EOS, S, C, BX, 0>), grid, block, 0, c->stream, src, dst, kp, flags);
     }
   } else {
-    if (c->lc.pipe2)
-      hipLaunchKernelGGL((k_step2_fe<EOS, S, C, BX, sizeof(S) == 4 ? 1 : 0>), grid, block, 0, c->stream,
-                         src, dst, kp, flags);
-    else
-      hipLaunchKernelGGL((k_step2_fe<EOS, S, C, BX, 0>), grid, block, 0, c->stream, src, dst, kp, flags);
+    hipLaunchKernelGGL((k_step2_fe<EOS, S, C, BX>), grid, block, 0, c->stream, src, dst, kp, flags);
   }
   c->cur ^= 1;
 }

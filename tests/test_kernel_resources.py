@@ -21,7 +21,7 @@ LLVM = "/opt/rocm/llvm/bin"
 DEFAULT_LAUNCHED = {
     "P periodic (pipelined, no register cap)": r"k_step_p_pipeILi[01]E(dd|ff)Li(64|256)ELi[01]ELi0EE",
     "P periodic, two steps per launch": r"k_step2_pILi[01]E(dd|ff)Li256ELi[01]EE",
-    "FE periodic, two steps per launch": r"k_step2_feILi[01]E(ddLi128ELi0|ffLi192ELi1)EE",
+    "FE periodic, two steps per launch": r"k_step2_feILi[01]E(ddLi128|ffLi192)EE",
     "FE FP64 periodic (register target 3)": r"k_step_feILi[01]EddLi(64|256)ELi[01]ELi3ELi0EE",
     "FE FP32 periodic (pipelined, register target 5)": r"k_step_fe_pipeILi[01]EffLi(64|256)ELi[01]ELi5EE",
     "P general (walls, drive)": r"k_step_pILi[01]E(dd|ff)Li(64|256)ELi1ELi0ELi1EE",
