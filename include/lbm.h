@@ -262,8 +262,12 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
  * graph.  Every check_every steps a checking step measures, per problem,
  * max |u(t) - u(t - check_every)|; a problem retires as converged when that
  * is below du_tol (or stays below 1e-6 without falling for 5 checks, the
- * floor of FP32 storage), or as unstable when it raises NONFINITE or
- * EOS_DOMAIN.  Retired problems keep their state for lbm_batch_observe(). */
+ * floor of FP32 storage), as unstable when it raises NONFINITE or
+ * EOS_DOMAIN, or as stalled when that maximum has not fallen below its
+ * lowest value for LBM_BATCH_STALL_CHECKS checks without either rule being
+ * met (its velocity field stopped settling: it would run to any step limit
+ * without converging).  Retired problems keep their state for
+ * lbm_batch_observe(). */
 typedef struct lbm_batch lbm_batch;
 
 #define LBM_BATCH_ACTIVE 0
@@ -271,6 +275,9 @@ typedef struct lbm_batch lbm_batch;
 #define LBM_BATCH_UNSTABLE 2
 #define LBM_BATCH_MAXSTEPS 3
 #define LBM_BATCH_DROPPED 4 /* retired because its partner became unstable */
+#define LBM_BATCH_STALLED 5 /* no new lowest max |du| in LBM_BATCH_STALL_CHECKS
+                               checks, and not converged */
+#define LBM_BATCH_STALL_CHECKS 100
 
 lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, size_t* bytes);
 

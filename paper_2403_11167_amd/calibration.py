@@ -553,6 +553,7 @@ def steps_by_class(tuples, sizes, info):
     return {key: dict(lattices=len(v), median_steps=int(np.median([a for a, _ in v])),
                       max_steps=int(max(a for a, _ in v)),
                       at_cap=int(sum(1 for _, st in v if st == lbm.BATCH_MAXSTEPS)),
+                      stalled=int(sum(1 for _, st in v if st == lbm.BATCH_STALLED)),
                       unstable=int(sum(1 for _, st in v if st in (lbm.BATCH_UNSTABLE,
                                                                     lbm.BATCH_DROPPED))))
             for key, v in sorted(out.items())}

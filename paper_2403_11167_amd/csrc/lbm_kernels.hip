@@ -3410,6 +3410,9 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
       if (conv) {
         I.state = LBM_BATCH_CONVERGED;
         b->tables_valid = false;
+      } else if (I.stall >= LBM_BATCH_STALL_CHECKS) {
+        I.state = LBM_BATCH_STALLED;
+        b->tables_valid = false;
       }
     }
   }

@@ -24,6 +24,7 @@ BOUNDARY_PERIODIC, BOUNDARY_WALLS = 0, 1
 FLAG_NONFINITE, FLAG_PSI_CLAMP, FLAG_EOS_DOMAIN = 1, 2, 4
 
 BATCH_ACTIVE, BATCH_CONVERGED, BATCH_UNSTABLE, BATCH_MAXSTEPS, BATCH_DROPPED = 0, 1, 2, 3, 4
+BATCH_STALLED, BATCH_STALL_CHECKS = 5, 100
 KF_SET, KF_NT_STORE, KF_REGCAP, KF_PIPELINE, KF_NO_XCD_REMAP, KF_TWO_STEP, KF_STRIP128 = (
     0x80000000, 1, 2, 4, 8, 16, 32)
 KF_STRIP192 = 64

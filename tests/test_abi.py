@@ -23,6 +23,16 @@ def test_header_and_binding_agree():
     assert header_functions() == sorted(lbm.EXPORTED_SYMBOLS)
 
 
+def test_header_constants_match_the_binding():
+    """Every LBM_KF_*, LBM_BATCH_* and LBM_FLAG_* value of the header is the
+    binding's constant of the same name."""
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    defs = dict(re.findall(r"^#define\s+LBM_((?:KF|BATCH|FLAG)_\w+)\s+(0x[0-9a-fA-F]+|\d+)", src, re.M))
+    assert len(defs) >= 15
+    for name, val in defs.items():
+        assert getattr(lbm, name) == int(val, 0), name
+
+
 def test_every_declared_symbol_is_exported():
     L = lbm.lib()
     for name in header_functions():
