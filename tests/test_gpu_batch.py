@@ -257,21 +257,23 @@ def test_persistent_tile_loop_and_stats():
 
 
 def test_stalled_problem_retires():
-    """A uniform lattice under a constant body force accelerates forever: its
-    max |u(t) - u(t - K)| stays at F K / rho, never reaches a new lowest
-    value, and the problem retires as stalled after LBM_BATCH_STALL_CHECKS
-    checks (the first check only stores u); a problem at rest beside it
+    """A uniform lattice under a constant body force accelerates for ever:
+    its max |u(t) - u(t - K)| stays at about F K / rho (above the FP32 floor
+    rule's 1e-6) and only rounding decides whether a check sets a new lowest
+    value, so a run of LBM_BATCH_STALL_CHECKS checks without one soon comes
+    and the problem retires as stalled; a problem at rest beside it
     converges."""
     a = 0.25
     T = cs_T(a, 0.8)
     rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
-    c0 = lbm.Config(32, 16, 1, lbm.EOS_CS, a, 4.0, 1.0, T, kappa=0.5, fx=1e-7)
+    c0 = lbm.Config(32, 16, 1, lbm.EOS_CS, a, 4.0, 1.0, T, kappa=0.5, fx=1e-5)
     c1 = lbm.Config(32, 16, 1, lbm.EOS_CS, a, 4.0, 1.0, T, kappa=0.5)
     r0 = np.full((16, 32), rl)
     b = lbm.Batch([c0, c1], [to_dev(r0), to_dev(r0)])
     K = 2
-    b.run(check_every=K, du_tol=1e-12, max_steps=K * (lbm.BATCH_STALL_CHECKS + 10))
-    st, nsteps, du, _ = b.state()
-    assert st == [lbm.BATCH_STALLED, lbm.BATCH_CONVERGED], (st, du)
-    assert nsteps[0] == K * (lbm.BATCH_STALL_CHECKS + 2)
+    b.run(check_every=K, du_tol=1e-12, max_steps=K * 20 * lbm.BATCH_STALL_CHECKS)
+    st, nsteps, du, fl = b.state()
+    assert st == [lbm.BATCH_STALLED, lbm.BATCH_CONVERGED], (st, du, nsteps)
+    assert nsteps[0] >= K * (lbm.BATCH_STALL_CHECKS + 2)
+    assert du[0] > 1e-6 and fl[0] == 0
     b.close()
