@@ -1083,13 +1083,18 @@ __device__ __forceinline__ void tile_p2(const S* __restrict__ src, S* __restrict
 // output is rounded to the storage type, so two steps of this kernel equal
 // two single steps bit for bit.
 // The first step's row r-2 reaches the collision in one of two ways:
-//   HOLD = 0 (FP64, whose registers are spent): pulled a second time in
-//            phase 2, two iterations after A pulled it;
+//   HOLD = 0 (FP64, whose registers are spent): pulled a second time, two
+//            iterations after A pulled it; that pull is issued at the start
+//            of phase 1 and A's pull of the next row at the end of phase 2,
+//            after the collisions, so that each is in flight through a
+//            phase of work without adding to the registers the collisions
+//            need;
 //   HOLD = 1 (FP32): A's rows are kept in registers for two iterations, and
 //            the pull of row r+1 is issued in phase 1 for the next
-//            iteration's A, unconditionally (a lane without a column reads
-//            a valid one), so that it stays in flight through phase 2
-//            (see tile_p_pipe); 27 more registers per lane.
+//            iteration's A, so that it stays in flight through phase 2; 27
+//            more registers per lane.
+// Early pulls are unconditional (a lane without a column reads a valid one),
+// so that a wait for one leaves the later ones in flight (see tile_p_pipe).
 template <int EOS, class S, class C, int BX, int NT, int HOLD>
 __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restrict__ dst,
                                          const KParams<C>& kp, unsigned* __restrict__ flags,
@@ -1143,20 +1148,17 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
 
   const int ra = y0 - 5;  // first-step row fetched at k = 0
   const int niter = ly + 11;
-  C gA[9];         // HOLD: row r, fetched one iteration ahead
+  C gA[9];         // row r, fetched one iteration ahead
   C h1[9], h2[9];  // HOLD: rows r-1 and r-2 as A pulled them
-  if constexpr (HOLD) pull(ra, gA);
+  C gC[9];         // !HOLD: row r-2, pulled again at the start of phase 1
+  pull(ra, gA);
   for (int k = 0; k < niter; ++k) {
     const int r = ra + k;
     // ---- phase 0: A(r), D(r-3)
     C g[9];
     if (r <= y0 + ly + 4 && dA) {
-      if constexpr (HOLD) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = gA[i];
-      } else {
-        pull(r, g);
-      }
+      for (int i = 0; i < 9; ++i) g[i] = gA[i];
       const C dr = sum9(g);
       if (own) fl |= domain_flags<MODEL_FE, EOS>(kp.rho_ref + dr, kp);
       rho1[r & 3][off + 5] = dr;
@@ -1182,6 +1184,7 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
     __syncthreads();
     // ---- phase 1: B(r-1), E(r-5)
     if constexpr (HOLD) pull(r + 1, gA);
+    else pull(r - 2, gC);
     if (r - 1 >= y0 - 4 && r - 1 <= y0 + ly + 3 && dB)
       mu1[(r - 1) & 3][off + 4] = mu_at(rho1[(r - 2) & 3], rho1[(r - 1) & 3], rho1[r & 3], off + 5);
     if (r - 5 >= y0 - 1 && r - 5 <= y0 + ly && dE)
@@ -1191,12 +1194,8 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
     const int c = r - 2;
     if (c >= y0 - 3 && c <= y0 + ly + 2 && dC) {
       C g[9];
-      if constexpr (HOLD) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = h2[i];
-      } else {
-        pull(c, g);
-      }
+      for (int i = 0; i < 9; ++i) g[i] = HOLD ? h2[i] : gC[i];
       const C d0 = sum9(g);
       C v[9], m[9];
       gather(rho1[(c - 1) & 3], rho1[c & 3], rho1[(c + 1) & 3], off + 5, v);
@@ -1242,6 +1241,7 @@ __device__ __forceinline__ void tile_fe2(const S* __restrict__ src, S* __restric
 #pragma unroll
       for (int i = 0; i < 9; ++i) st<NT>(&dst[o + 64 * i], (S)R0[i]);
     }
+    if constexpr (!HOLD) pull(r + 1, gA);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
