@@ -259,7 +259,14 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
  * parameters may differ; the precision is common) in lockstep: each time
  * step is one launch per (model, EOS, strip width) group over a table of all
  * tiles of all active problems, and runs of steps are captured in a HIP
- * graph.  Every check_every steps a checking step measures, per problem,
+ * graph.  Problems on 256-column strips whose kernel_flags allow two steps
+ * per launch (0, or LBM_KF_TWO_STEP set) form groups of their own that take
+ * two steps per launch, except the last two steps of each check interval;
+ * results are the same bit for bit.  A problem with tile_y = 0 has its
+ * segment height chosen again for its group whenever the active problems
+ * change (8 to 128 rows: the tallest whose tiles fill about one round of
+ * resident workgroups); tile_rounds is ignored in a batch.  Every
+ * check_every steps a checking step measures, per problem,
  * max |u(t) - u(t - check_every)|; a problem retires as converged when that
  * is below du_tol (or stays below 1e-6 without falling for 5 checks, the
  * floor of FP32 storage), as unstable when it raises NONFINITE or
@@ -320,6 +327,13 @@ lbm_status lbm_batch_set_partner(lbm_batch* b, int32_t i, int32_t j);
  * NULL.  Host only. */
 lbm_status lbm_batch_stats(const lbm_batch* b, int64_t* node_updates, double* gpu_ms,
                            int64_t* chunks);
+
+/* The launch shape of problem i in the batch (not part of the paper's
+ * method): steps_per_launch 2 when its group takes two steps per launch,
+ * strip and threads of that kernel, segment its current segment height
+ * (with tile_y = 0 it may change whenever the active problems change), and
+ * workgroups its number of tiles.  Host only. */
+lbm_status lbm_batch_launch_info(const lbm_batch* b, int32_t i, lbm_launch* out);
 
 /* Per-problem state (LBM_BATCH_*), steps taken, last measured max |du| and
  * sticky flags; each pointer may be NULL, else points to n elements. */

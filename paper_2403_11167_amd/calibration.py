@@ -219,19 +219,39 @@ def build_problems(tuples, sizes, precision, guesses=None, tiles=None):
     return cfgs, rho0s, meta
 
 
-TILE_CANDIDATES = ((64, 8), (64, 16), (64, 32), (64, 64), (256, 8), (256, 16), (256, 32),
-                   (256, 64))
+# (strip width, segment height); height 0: chosen by the batch for each
+# group from its active lattices at every retirement
+TILE_CANDIDATES = ((64, 0), (64, 8), (64, 16), (64, 32), (256, 0), (256, 8), (256, 16),
+                   (256, 32), (256, 64))
+# a fixed height must beat the automatic one by this factor to be chosen:
+# the timing covers the full class, while the automatic height also follows
+# the class as its lattices retire
+AUTO_MARGIN = 0.95
+
+
+def class_counts(tuples, sizes):
+    """Lattices per size class (model, L): each tuple has a flat and a
+    droplet lattice of its model."""
+    out = {}
+    for t, size in zip(tuples, sizes):
+        fx, fy, L = _shape(size)
+        for key in ((t.model, fx, fy), (t.model, L, L)):
+            out[key] = out.get(key, 0) + 1
+    return out
 
 
 def autotune_batch_tiles(precision=lbm.FP32_SHIFTED, sizes=SIZES, steps=40, nodes=1 << 20,
-                         log=None):
+                         counts=None, log=None):
     """The batch tile shape (tile_x, tile_y) of each size class (model, L x L)
     of the calibration: for every class, a batch of flat-interface lattices
-    of that class (about `nodes` nodes in all, mid-range tuple Tr = 0.75,
-    w = 5, kappa = 1.25) runs `steps` lockstep steps per candidate shape,
-    timed by the batch's own GPU clock (lbm_batch_stats); the least GPU time
-    per node update wins.  Strips of 256 columns are tried where L >= 256.
-    Returns {(model, L, L): (tile_x, tile_y)} and the timings."""
+    of that class (counts[(model, L, L)] of them when given, the class's
+    share of the batch to be run, else about `nodes` nodes; mid-range tuple
+    Tr = 0.75, w = 5, kappa = 1.25) runs `steps` lockstep steps per candidate
+    shape, timed by the batch's own GPU clock (lbm_batch_stats).  Strips of
+    256 columns are tried where L >= 256 (they take two steps per launch).
+    The automatic height (0) is kept unless a fixed one takes less than
+    AUTO_MARGIN of its GPU time per node update.  Returns
+    {(model, L, L): (tile_x, tile_y)} and the timings."""
     import torch
     say = log or (lambda *a: None)
     dev = torch.device("cuda:0")
@@ -240,7 +260,7 @@ def autotune_batch_tiles(precision=lbm.FP32_SHIFTED, sizes=SIZES, steps=40, node
         t = Tuple4(model, 0.75, 5.0, 1.25)
         rl, rv, W = initial_guess(t)
         for L in sizes:
-            n = max(2, nodes // (L * L))
+            n = (counts or {}).get((model, L, L), 0) or max(2, nodes // (L * L))
             rho = torch.from_numpy(flat_rho0(L, L, rl, rv, W)).to(dev)
             timings = []
             for tx, ty in TILE_CANDIDATES:
@@ -253,12 +273,16 @@ def autotune_batch_tiles(precision=lbm.FP32_SHIFTED, sizes=SIZES, steps=40, node
                 b.close()
                 timings.append((st["gpu_ms"] * 1e6 / max(st["node_updates"], 1), tx, ty))
             ns, tx, ty = min(timings)
+            if ty != 0:
+                auto = min((v, a, c) for v, a, c in timings if c == 0)
+                if ns >= AUTO_MARGIN * auto[0]:
+                    ns, tx, ty = auto
             best[(model, L, L)] = (tx, ty)
             table.append(dict(model="P" if model == lbm.MODEL_P else "FE", L=L, lattices=n,
                               tile_x=tx, tile_y=ty, ns_per_node_update=ns,
                               candidates={f"{a}x{c}": v for v, a, c in timings}))
-            say(f"batch tiles: {'P' if model == lbm.MODEL_P else 'FE'} L={L}: {tx}x{ty}, "
-                f"{ns:.4f} ns per node update")
+            say(f"batch tiles: {'P' if model == lbm.MODEL_P else 'FE'} L={L} ({n} lattices): "
+                f"{tx}x{ty or 'auto'}, {ns:.4f} ns per node update")
     return best, table
 
 
@@ -598,7 +622,7 @@ def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_
     pred_only = sur.predict(feats)
     infer_s = time.perf_counter() - t2
     t3 = time.perf_counter()
-    tiles, tile_table = autotune_batch_tiles(log=say)
+    tiles, tile_table = autotune_batch_tiles(counts=class_counts(tup, sizes), log=say)
     tune_s = time.perf_counter() - t3
     lab_p, inf_p = run_calibration(tup, sizes, max_steps=max_steps, tiles=tiles)
     say(f"plain: {inf_p['seconds']:.1f} s, {inf_p['converged_units']} tuples")

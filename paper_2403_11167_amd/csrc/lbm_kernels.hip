@@ -1692,6 +1692,30 @@ void k_batch_step(const BatchTile* __restrict__ tiles, const int* __restrict__ c
   }
 }
 
+// Two steps of every tile in the table (tile_p2 / tile_fe2, BX + 64 threads,
+// the same row schedules and register choices as k_step2_p / k_step2_fe),
+// walking the table as k_batch_step does.  Tiles are the single-step
+// kernel's (strips of BX columns, the problem's segment height), so one table
+// serves both kernels.
+template <int MODEL, int EOS, class S, class C, int BX>
+__global__ __launch_bounds__(BX + 64)
+void k_batch_step2(const BatchTile* __restrict__ tiles, const int* __restrict__ count,
+                   const InstDesc<C>* __restrict__ inst, int parity) {
+  const int n = *count;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const BatchTile bt = tiles[t];
+    const InstDesc<C>* d = inst + bt.inst;
+    const S* src = (const S*)(parity ? d->fB : d->fA);
+    S* dst = (S*)(parity ? d->fA : d->fB);
+    if constexpr (MODEL == MODEL_P)
+      tile_p2<EOS, S, C, BX, 1, sizeof(S) == 8 ? 1 : 0>(src, dst, d->kp, d->flags, bt.x0, bt.y0);
+    else
+      tile_fe2<EOS, S, C, BX, 1, sizeof(S) == 4 ? 1 : 0>(src, dst, d->kp, d->flags, bt.x0,
+                                                       bt.y0);
+    __syncthreads();  // the next tile reuses the LDS rings
+  }
+}
+
 // ---- initial state ------------------------------------------------------------
 // Stored g*_i(x) = f^eq_i(rho0(x + c_i), 0) - s_i, so that the first pull
 // yields f_i(x) = f^eq_i(rho0(x), 0) (Eq. 4: w_i rho; Eq. 20: rho delta_i0).
@@ -2929,12 +2953,17 @@ struct BatchInst {
   uint32_t flags;
   int64_t limit;    // retire with LBM_BATCH_MAXSTEPS once steps >= limit
   int partner;      // the other problem of its unit, or -1
+  int auto_ly;      // segment height chosen per group at each table rebuild
 };
 
+// two: the group's chunks take two steps per launch (k_batch_step2)
 struct GroupKey {
-  int model, eos, bx;
+  int model, eos, bx, two;
   bool operator<(const GroupKey& o) const {
-    return model != o.model ? model < o.model : eos != o.eos ? eos < o.eos : bx < o.bx;
+    return model != o.model ? model < o.model
+         : eos != o.eos     ? eos < o.eos
+         : bx != o.bx       ? bx < o.bx
+                            : two < o.two;
   }
 };
 
@@ -2957,9 +2986,11 @@ struct lbm_batch {
   // launch a grid set when the graph is captured; retirement changes the
   // tables and counts, and a new graph is captured only when a group
   // empties or its grid exceeds twice its tiles
+  // grid / resident: the single-step launches; grid2 / resident2: the
+  // two-step launches of a two-step group
   struct Group {
     GroupKey key;
-    int offset, capacity, count, grid, resident;
+    int offset, capacity, count, grid, resident, grid2, resident2;
   };
   std::vector<Group> groups;
   bool tables_valid;
@@ -2981,7 +3012,11 @@ struct BatchLayout {
   std::vector<size_t> inst_off, chk_off;
   size_t desc_off, tiles_off, du_off, flagptr_off, flagout_off, counts_off, total, tiles_cap;
 };
-constexpr int kMaxGroups = 8;  // 2 models x 2 EOS x 2 strip widths
+constexpr int kMaxGroups = 12;  // 2 models x 2 EOS x (64, 256, 256 two-step)
+// Automatic segment heights in a batch: the lowest, which sizes the tile
+// tables, and the candidates above it, tallest first.
+constexpr int kBatchMinLY = 8;
+constexpr int kBatchLY[] = {128, 64, 32, 16};
 
 BatchLayout make_batch_layout(int n, const lbm_params* p) {
   BatchLayout B;
@@ -2995,7 +3030,8 @@ BatchLayout make_batch_layout(int n, const lbm_params* p) {
     B.chk_off.push_back(off);
     off += align_up(2 * N * es);
     LaunchCfg lc = resolve_launch(&p[i]);
-    tiles += (size_t)((p[i].nx + lc.bx - 1) / lc.bx) * ((p[i].ny + lc.ly - 1) / lc.ly);
+    const int ly = p[i].tile_y > 0 ? lc.ly : kBatchMinLY;
+    tiles += (size_t)((p[i].nx + lc.bx - 1) / lc.bx) * ((p[i].ny + ly - 1) / ly);
   }
   size_t desc = std::max(sizeof(InstDesc<double>), sizeof(InstDesc<float>));
   B.desc_off = off;
@@ -3029,50 +3065,125 @@ int resident_blocks(K kernel, int bx) {
   return blocks * cus;
 }
 
-// chk < 0: only fix the group's grid (about one round of resident
-// workgroups, at most one per active tile), outside any capture
+// Launch kinds of one group: plain step, checking step, two steps.
+enum BatchLaunch { BL_RESIDENT = -2, BL_GRID = -1, BL_PLAIN = 0, BL_CHECK = 1, BL_TWO = 2 };
+
+// BL_RESIDENT: only find the group's resident workgroups per kernel;
+// BL_GRID: also fix its grids (about one round of resident workgroups, at
+// most one per active tile), outside any capture
 template <int MODEL, int EOS, class S, class C, int BX>
-void launch_batch_group(lbm_batch* b, lbm_batch::Group& g, int chk) {
-  if (chk < 0) {
+void launch_batch_group(lbm_batch* b, lbm_batch::Group& g, int kind, int parity) {
+  if (kind == BL_RESIDENT || kind == BL_GRID) {
     if (g.resident == 0) g.resident = resident_blocks(k_batch_step<MODEL, EOS, S, C, BX, 1, 0>, BX);
-    g.grid = std::max(1, std::min(g.count, g.resident));
+    if constexpr (BX == 256)
+      if (g.key.two && g.resident2 == 0)
+        g.resident2 = resident_blocks(k_batch_step2<MODEL, EOS, S, C, BX>, BX + 64);
+    if (kind == BL_GRID) {
+      g.grid = std::max(1, std::min(g.count, g.resident));
+      if (g.key.two) g.grid2 = std::max(1, std::min(g.count, g.resident2));
+    }
     return;
   }
   const InstDesc<C>* desc = (const InstDesc<C>*)(b->ws + b->desc_off);
   const BatchTile* tiles = (const BatchTile*)(b->ws + b->tiles_off) + g.offset;
   const int* count = (const int*)(b->ws + b->counts_off) + (&g - b->groups.data());
-  if (chk)
+  if (kind == BL_CHECK)
     hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 1>), dim3(g.grid), dim3(BX), 0,
-                       b->launch, tiles, count, desc, b->parity);
-  else
+                       b->launch, tiles, count, desc, parity);
+  else if (kind == BL_PLAIN)
     hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 0>), dim3(g.grid), dim3(BX), 0,
-                       b->launch, tiles, count, desc, b->parity);
+                       b->launch, tiles, count, desc, parity);
+  else if constexpr (BX == 256)
+    hipLaunchKernelGGL((k_batch_step2<MODEL, EOS, S, C, BX>), dim3(g.grid2), dim3(BX + 64), 0,
+                       b->launch, tiles, count, desc, parity);
 }
 
 template <class S, class C>
-void batch_step_typed(lbm_batch* b, int chk) {
-  for (auto& g : b->groups) {
-    if (chk >= 0 && g.count == 0) continue;  // no launch for an empty group
-    const GroupKey& k = g.key;
+void batch_group_typed(lbm_batch* b, lbm_batch::Group& g, int kind, int parity) {
+  const GroupKey& k = g.key;
 #define LBM_GROUP(M, E, X)                                                       \
-  if (k.model == M && k.eos == E && k.bx == X) launch_batch_group<M, E, S, C, X>(b, g, chk)
-    LBM_GROUP(MODEL_P, EOS_CS, 64);
-    LBM_GROUP(MODEL_P, EOS_CS, 256);
-    LBM_GROUP(MODEL_P, EOS_VDW, 64);
-    LBM_GROUP(MODEL_P, EOS_VDW, 256);
-    LBM_GROUP(MODEL_FE, EOS_CS, 64);
-    LBM_GROUP(MODEL_FE, EOS_CS, 256);
-    LBM_GROUP(MODEL_FE, EOS_VDW, 64);
-    LBM_GROUP(MODEL_FE, EOS_VDW, 256);
+  if (k.model == M && k.eos == E && k.bx == X) launch_batch_group<M, E, S, C, X>(b, g, kind, parity)
+  LBM_GROUP(MODEL_P, EOS_CS, 64);
+  LBM_GROUP(MODEL_P, EOS_CS, 256);
+  LBM_GROUP(MODEL_P, EOS_VDW, 64);
+  LBM_GROUP(MODEL_P, EOS_VDW, 256);
+  LBM_GROUP(MODEL_FE, EOS_CS, 64);
+  LBM_GROUP(MODEL_FE, EOS_CS, 256);
+  LBM_GROUP(MODEL_FE, EOS_VDW, 64);
+  LBM_GROUP(MODEL_FE, EOS_VDW, 256);
 #undef LBM_GROUP
-  }
-  if (chk >= 0) b->parity ^= 1;
 }
 
-// chk: 1 checking step, 0 plain step, -1 fix the launch grids only
-void batch_step(lbm_batch* b, int chk) {
-  if (b->fp64) batch_step_typed<double, double>(b, chk);
-  else batch_step_typed<float, float>(b, chk);
+void batch_group(lbm_batch* b, lbm_batch::Group& g, int kind, int parity) {
+  if (b->fp64) batch_group_typed<double, double>(b, g, kind, parity);
+  else batch_group_typed<float, float>(b, g, kind, parity);
+}
+
+// A problem takes two steps per launch in a batch when its launch
+// configuration asks for them and its tiles are 256-column strips (the
+// two-step row schedules need the halo wavefront beside the strip).
+int batch_two(const lbm_ctx* c) { return c->lc.two && c->lc.bx == 256 ? 1 : 0; }
+
+// Two-step launches of a two-step group in a chunk of `steps` (even) steps:
+// the last two steps are single (the last one checking), and the launch
+// count steps - m is kept even, so that every chunk ends in the buffer it
+// started from.
+int batch_pairs(const lbm_batch::Group& g, int steps) {
+  return g.key.two ? ((steps - 2) / 2) & ~1 : 0;
+}
+
+template <class C>
+InstDesc<C> make_desc(lbm_batch* b, int i) {
+  InstDesc<C> d{};
+  const BatchInst& I = b->inst[i];
+  lbm_ctx* c = I.ctx;
+  if constexpr (sizeof(C) == 8) d.kp = c->kd; else d.kp = c->kf;
+  d.fA = c->ws + c->L.fA;
+  d.fB = c->ws + c->L.fB;
+  size_t N = (size_t)c->p.nx * c->p.ny;
+  d.uxp = (C*)(b->ws + I.chk_off);
+  d.uyp = d.uxp + N;
+  d.flags = (unsigned*)(c->ws + c->L.flags);
+  d.du = (unsigned long long*)(b->ws + b->du_off) + i;
+  return d;
+}
+
+// Enqueue the copy of every instance's descriptor (launch parameters and
+// buffers) to the device; `host` must stay alive until the stream has
+// passed the copy.
+lbm_status upload_descs(lbm_batch* b, std::vector<char>& host) {
+  const size_t dsz = b->fp64 ? sizeof(InstDesc<double>) : sizeof(InstDesc<float>);
+  host.assign(b->n * dsz, 0);
+  for (int i = 0; i < b->n; ++i) {
+    if (b->fp64) {
+      InstDesc<double> d = make_desc<double>(b, i);
+      memcpy(&host[i * dsz], &d, dsz);
+    } else {
+      InstDesc<float> d = make_desc<float>(b, i);
+      memcpy(&host[i * dsz], &d, dsz);
+    }
+  }
+  return hipMemcpyAsync(b->ws + b->desc_off, host.data(), host.size(), hipMemcpyHostToDevice,
+                        b->stream) == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+// Segment height of a group's automatic-height lattices: the tallest
+// candidate whose tiles (with the other lattices' own) fill at least three
+// quarters of one round of the group's resident workgroups, else the lowest.
+// Taller segments repeat fewer halo rows (a two-step free-energy segment
+// re-runs ten), so they win while the tiles still fill the device; once few
+// lattices remain, shorter ones keep more workgroups busy.
+int batch_group_ly(const lbm_batch* b, const lbm_batch::Group& g, const std::vector<int>& act) {
+  const int64_t G = g.key.two ? g.resident2 : g.resident;
+  for (int ly : kBatchLY) {
+    int64_t T = 0;
+    for (int i : act) {
+      const lbm_ctx* c = b->inst[i].ctx;
+      T += (int64_t)c->nstrips * (b->inst[i].auto_ly ? (c->p.ny + ly - 1) / ly : c->nseg);
+    }
+    if (4 * T >= 3 * G) return ly;
+  }
+  return kBatchMinLY;
 }
 
 // Rebuild the tile tables of the active instances, largest first within
@@ -3094,21 +3205,50 @@ lbm_status rebuild_tables(lbm_batch* b) {
     std::map<GroupKey, int> cap;
     for (int i = 0; i < b->n; ++i) {
       lbm_ctx* c = b->inst[i].ctx;
-      cap[GroupKey{c->p.model, c->p.eos, c->lc.bx}] += c->nseg * c->nstrips;
+      cap[GroupKey{c->p.model, c->p.eos, c->lc.bx, batch_two(c)}] += c->nseg * c->nstrips;
     }
     int off = 0;
     for (auto& kv : cap) {
-      b->groups.push_back({kv.first, off, kv.second, 0, 0, 0});
+      b->groups.push_back({kv.first, off, kv.second, 0, 0, 0, 0, 0});
       off += kv.second;
     }
     if ((size_t)off > b->tiles_cap || b->groups.size() > (size_t)kMaxGroups)
       return LBM_ERR_WORKSPACE;
   }
+  // automatic segment heights, per group, from the active lattices
+  std::vector<char> descs;
+  bool relaunch = false;
+  for (auto& g : b->groups) {
+    std::vector<int> act;
+    bool any_auto = false;
+    for (int i = 0; i < b->n; ++i) {
+      const BatchInst& I = b->inst[i];
+      const lbm_ctx* c = I.ctx;
+      if (I.state != LBM_BATCH_ACTIVE || c->p.model != g.key.model || c->p.eos != g.key.eos ||
+          c->lc.bx != g.key.bx || batch_two(c) != g.key.two)
+        continue;
+      act.push_back(i);
+      any_auto |= I.auto_ly != 0;
+    }
+    if (!any_auto) continue;
+    batch_group(b, g, BL_RESIDENT, 0);
+    const int ly = batch_group_ly(b, g, act);
+    for (int i : act) {
+      lbm_ctx* c = b->inst[i].ctx;
+      if (b->inst[i].auto_ly && c->lc.ly != ly) {
+        c->lc.ly = ly;
+        apply_launch(c);
+        relaunch = true;
+      }
+    }
+  }
+  if (relaunch && (upload_descs(b, descs) != LBM_OK || hipStreamSynchronize(b->stream) != hipSuccess))
+    return LBM_ERR_HIP;
   for (int i : order) {
     BatchInst& I = b->inst[i];
     if (I.state != LBM_BATCH_ACTIVE) continue;
     lbm_ctx* c = I.ctx;
-    GroupKey key{c->p.model, c->p.eos, c->lc.bx};
+    GroupKey key{c->p.model, c->p.eos, c->lc.bx, batch_two(c)};
     auto& v = tabs[key];
     for (int s = 0; s < c->nseg; ++s)
       for (int x = 0; x < c->nstrips; ++x) v.push_back(BatchTile{i, x * c->lc.bx, s * c->lc.ly, 0});
@@ -3148,11 +3288,19 @@ __global__ void k_gather_flags(const unsigned* const* __restrict__ ptrs, unsigne
 
 // A launch with more than twice as many workgroups as tiles wastes its
 // dispatch on workgroups that exit at once (the tail of a run, when a few
-// slow lattices remain): then the graph is captured again with smaller
+// slow lattices remain), and one with fewer workgroups than it could keep
+// resident walks 1.5 times as many tiles (after shorter automatic segments)
+// in more rounds than needed: then the graph is captured again with new
 // grids, which happens a few times per group as its lattices retire.
-bool grids_oversized(const lbm_batch* b) {
-  for (const auto& g : b->groups)
-    if (g.count > 0 && 2 * g.count < g.grid) return true;
+bool grids_mismatched(const lbm_batch* b) {
+  auto off = [](int count, int grid, int resident) {
+    return 2 * count < grid || (grid < resident && 2 * count > 3 * grid);
+  };
+  for (const auto& g : b->groups) {
+    if (g.count == 0) continue;
+    if (off(g.count, g.grid, g.resident)) return true;
+    if (g.key.two && off(g.count, g.grid2, g.resident2)) return true;
+  }
   return false;
 }
 
@@ -3169,28 +3317,36 @@ void drop_graph(lbm_batch* b) {
   b->graph_steps = 0;
 }
 
-// Capture `steps` lockstep steps (the last one checking) as one graph.  The
-// capture runs on the library's own stream (the caller's stream may be the
-// null stream, which cannot be captured); the graph is launched on the
-// caller's stream.  The du slots are cleared by a kernel, not a memset node.
+// Capture `steps` (even) lockstep steps as one graph: each group with
+// active tiles runs its steps in order (its lattices are independent of the
+// other groups'), the last one checking.  The capture runs on the library's
+// own stream (the caller's stream may be the null stream, which cannot be
+// captured); the graph is launched on the caller's stream.  The du slots
+// are cleared by a kernel, not a memset node, before any checking step.
 lbm_status capture_chunk(lbm_batch* b, int steps) {
   drop_graph(b);
-  batch_step(b, -1);  // launch grids from occupancy, before the capture
-  int parity0 = b->parity;
+  // launch grids from occupancy, before the capture
+  for (auto& g : b->groups) batch_group(b, g, BL_GRID, 0);
+  const int parity0 = b->parity;
   hipGraph_t g;
   if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return LBM_ERR_HIP;
   b->launch = b->cap_stream;
-  for (int s = 0; s < steps - 1; ++s) batch_step(b, 0);
   hipLaunchKernelGGL(k_zero_u64, dim3((b->n + 255) / 256), dim3(256), 0, b->cap_stream,
                      (unsigned long long*)(b->ws + b->du_off), b->n);
-  batch_step(b, 1);
+  for (auto& gr : b->groups) {
+    if (gr.count == 0) continue;  // no launch for an empty group
+    const int m = batch_pairs(gr, steps);
+    int par = parity0;
+    for (int s = 0; s < m; ++s, par ^= 1) batch_group(b, gr, BL_TWO, par);
+    for (int s = 2 * m; s < steps - 1; ++s, par ^= 1) batch_group(b, gr, BL_PLAIN, par);
+    batch_group(b, gr, BL_CHECK, par);
+  }
   hipLaunchKernelGGL(k_gather_flags, dim3((b->n + 255) / 256), dim3(256), 0, b->cap_stream,
                      (const unsigned* const*)(b->ws + b->flagptr_off),
                      (unsigned*)(b->ws + b->flagout_off), b->n);
   hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
   b->launch = b->stream;
-  b->parity = parity0;  // capture only recorded the launches
   if (e != hipSuccess) return LBM_ERR_HIP;
   e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
@@ -3204,19 +3360,6 @@ lbm_status capture_chunk(lbm_batch* b, int steps) {
   return LBM_OK;
 }
 
-template <class C>
-InstDesc<C> make_desc(lbm_batch* b, const BatchInst& I) {
-  InstDesc<C> d{};
-  lbm_ctx* c = I.ctx;
-  if constexpr (sizeof(C) == 8) d.kp = c->kd; else d.kp = c->kf;
-  d.fA = c->ws + c->L.fA;
-  d.fB = c->ws + c->L.fB;
-  size_t N = (size_t)c->p.nx * c->p.ny;
-  d.uxp = (C*)(b->ws + I.chk_off);
-  d.uyp = d.uxp + N;
-  d.flags = (unsigned*)(c->ws + c->L.flags);
-  return d;
-}
 
 }  // namespace
 
@@ -3283,9 +3426,13 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
   for (int i = 0; i < n && st == LBM_OK; ++i) {
     BatchInst& I = b->inst[i];
     I = BatchInst{nullptr, B.chk_off[i], LBM_BATCH_ACTIVE, 0, INFINITY, INFINITY, 0, 0, 0u,
-                  INT64_MAX, -1};
+                  INT64_MAX, -1, p[i].tile_y <= 0 ? 1 : 0};
     st = read_host(d_rho0[i], (size_t)p[i].nx * p[i].ny, stream, h);
     if (st == LBM_OK) st = ctx_setup(&p[i], b->ws + B.inst_off[i], d_rho0[i], h, stream, &I.ctx);
+    if (st == LBM_OK && I.auto_ly) {
+      I.ctx->lc.ly = kBatchMinLY;  // the height the tile tables are sized for
+      apply_launch(I.ctx);
+    }
   }
   if (st != LBM_OK) {
     for (auto& I : b->inst) delete I.ctx;
@@ -3296,24 +3443,13 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* p, const double* const*
     return st;
   }
   // instance descriptors
-  size_t dsz = b->fp64 ? sizeof(InstDesc<double>) : sizeof(InstDesc<float>);
-  std::vector<char> descs(n * dsz);
+  std::vector<char> descs;
   std::vector<unsigned*> flagptrs(n);
   for (int i = 0; i < n; ++i) {
     lbm_ctx* c = b->inst[i].ctx;
     flagptrs[i] = (unsigned*)(c->ws + c->L.flags);
-    if (b->fp64) {
-      InstDesc<double> d = make_desc<double>(b, b->inst[i]);
-      d.du = (unsigned long long*)(b->ws + b->du_off) + i;
-      memcpy(&descs[i * dsz], &d, dsz);
-    } else {
-      InstDesc<float> d = make_desc<float>(b, b->inst[i]);
-      d.du = (unsigned long long*)(b->ws + b->du_off) + i;
-      memcpy(&descs[i * dsz], &d, dsz);
-    }
   }
-  if (hipMemcpyAsync(b->ws + b->desc_off, descs.data(), descs.size(), hipMemcpyHostToDevice,
-                     stream) != hipSuccess ||
+  if (upload_descs(b, descs) != LBM_OK ||
       hipMemcpyAsync(b->ws + b->flagptr_off, flagptrs.data(), n * sizeof(unsigned*),
                      hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
@@ -3359,7 +3495,7 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t check_every, double du_tol, int64
     // (or refilled), which changes the launches the graph holds
     if (!b->tables_valid) {
       if ((st = rebuild_tables(b)) != LBM_OK) break;
-      if (group_mask(b) != b->graph_groups || grids_oversized(b)) drop_graph(b);
+      if (group_mask(b) != b->graph_groups || grids_mismatched(b)) drop_graph(b);
     }
     int chunk = (int)std::min<int64_t>(K, max_steps - done);
     chunk = std::max(2, chunk - (chunk & 1));
@@ -3508,6 +3644,19 @@ lbm_status lbm_batch_stats(const lbm_batch* b, int64_t* node_updates, double* gp
   if (node_updates) *node_updates = b->node_updates;
   if (gpu_ms) *gpu_ms = b->gpu_ms;
   if (chunks) *chunks = b->chunks;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_launch_info(const lbm_batch* b, int32_t i, lbm_launch* out) {
+  if (!b || i < 0 || i >= b->n || !out) return LBM_ERR_INVALID_ARG;
+  memset(out, 0, sizeof(*out));
+  const lbm_ctx* c = b->inst[i].ctx;
+  const int two = batch_two(c);
+  out->steps_per_launch = two ? 2 : 1;
+  out->strip = c->lc.bx;
+  out->threads = two ? c->lc.bx + 64 : c->lc.bx;
+  out->segment = c->lc.ly;
+  out->workgroups = c->nstrips * c->nseg;
   return LBM_OK;
 }
 

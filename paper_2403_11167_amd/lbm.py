@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = [
     "lbm_match_p_to_fe",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_state",
     "lbm_batch_observe", "lbm_batch_destroy", "lbm_batch_set_limit", "lbm_batch_set_partner",
-    "lbm_batch_stats",
+    "lbm_batch_stats", "lbm_batch_launch_info",
     "lbm_mlp_forward", "lbm_mlp_workspace_bytes", "lbm_mlp_grad", "lbm_mlp_adam",
     "lbm_mlp_train_step", "lbm_mlp_grad_noalloc",
 ]
@@ -150,6 +150,7 @@ def lib():
                                     ctypes.POINTER(ctypes.c_int64)]
         L.lbm_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.lbm_batch_launch_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Launch)]
         L.lbm_batch_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int64), D,
                                       ctypes.POINTER(ctypes.c_uint32)]
@@ -437,6 +438,13 @@ class Batch:
         _check(lib().lbm_batch_stats(self._h, ctypes.byref(nu), ctypes.byref(ms),
                                      ctypes.byref(ch)), "lbm_batch_stats")
         return dict(node_updates=nu.value, gpu_ms=ms.value, chunks=ch.value)
+
+    def launch_info(self, i: int) -> dict:
+        """Problem i's launch shape in the batch (see lbm_batch_launch_info)."""
+        out = Launch()
+        _check(lib().lbm_batch_launch_info(self._h, int(i), ctypes.byref(out)),
+               "lbm_batch_launch_info")
+        return out.as_dict()
 
     def state(self):
         """(state, steps, du, flags) lists."""

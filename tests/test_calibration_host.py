@@ -53,3 +53,17 @@ def test_each_tuple_is_one_unit():
     r = Rec()
     cal.pair_units(r, meta)
     assert r.pairs == [(0, 1), (2, 3), (4, 5)]
+
+
+def test_class_counts_cover_both_lattices_of_each_tuple():
+    """The tile autotuner times each size class at the number of lattices it
+    has in the batch: one flat and one droplet lattice per tuple, keyed by
+    (model, nx, ny)."""
+    tuples = [cal.Tuple4(lbm.MODEL_P, 0.8, 5.0, 1.0), cal.Tuple4(lbm.MODEL_FE, 0.8, 5.0, 1.0),
+              cal.Tuple4(lbm.MODEL_P, 0.7, 4.0, 1.5)]
+    counts = cal.class_counts(tuples, [256, 64, (64, 8, 128)])
+    assert counts == {(lbm.MODEL_P, 256, 256): 2, (lbm.MODEL_FE, 64, 64): 2,
+                      (lbm.MODEL_P, 64, 8): 1, (lbm.MODEL_P, 128, 128): 1}
+    held = cal.sample_tuples(64, 6)
+    sizes = cal.sample_sizes(64, 6)
+    assert sum(cal.class_counts(held, sizes).values()) == 2 * 64

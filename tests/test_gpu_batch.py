@@ -277,3 +277,96 @@ def test_stalled_problem_retires():
     assert nsteps[0] >= K * (lbm.BATCH_STALL_CHECKS + 2)
     assert du[0] > 1e-6 and fl[0] == 0
     b.close()
+
+
+@pytest.mark.parametrize("precision", [lbm.FP64, lbm.FP32_SHIFTED])
+def test_two_step_groups_equal_single_runs(precision):
+    """Problems on 256-column tiles take two steps per launch in a batch
+    (k_batch_step2), beside problems that take one: ragged strips and
+    segments, both models, both equations of state, and chunks whose pair
+    count is rounded down to even (8 steps: two pairs and four single steps;
+    12 steps: four pairs and four) or not (10 steps: four pairs and two).
+    A free-energy problem that asks for single steps on the same strip width
+    forms its own group.  Every lattice equals the same lattice run alone,
+    bit for bit, after runs resumed across three chunk lengths."""
+    a = 0.25
+    T = cs_T(a, 0.8)
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    Tv = 0.9 * 4 / 7
+    rlv, rvv, _ = th.maxwell(th.VDW, 9 / 49, 2 / 21, 1.0, Tv)
+    tauF = [1.0] * 9
+    tauF[1] = 0.75
+    single = lbm.KF_SET | lbm.KF_NT_STORE
+    cases = [
+        (lbm.Config(256, 40, 0, lbm.EOS_CS, a, 4.0, 1.0, T, sigma_li=0.1, kappa_p=0.9,
+                    precision=precision).with_launch(256, 8, 0), 0.5 * (rl + rv), 21),
+        (lbm.Config(320, 24, 1, lbm.EOS_CS, a, 4.0, 1.0, T, tau=tauF, kappa=0.5,
+                    precision=precision).with_launch(256, 16, 0), 0.5 * (rl + rv), 22),
+        (lbm.Config(300, 20, 0, lbm.EOS_VDW, 9 / 49, 2 / 21, 1.0, Tv,
+                    precision=precision).with_launch(256, 8, 0), 0.5 * (rlv + rvv), 23),
+        (lbm.Config(256, 32, 1, lbm.EOS_CS, a, 4.0, 1.0, T, kappa=0.5,
+                    precision=precision).with_launch(256, 8, single), 0.5 * (rl + rv), 24),
+        (lbm.Config(64, 48, 0, lbm.EOS_CS, a, 4.0, 1.0, T, sigma_li=0.1, kappa_p=0.9,
+                    precision=precision).with_launch(64, 8, 0), 0.5 * (rl + rv), 25),
+    ]
+    cfgs = [c for c, _, _ in cases]
+    r0s = [inputs.spinodal(c.nx, c.ny, m, 0.01, seed=s) for c, m, s in cases]
+    b = lbm.Batch(cfgs, [to_dev(r) for r in r0s])
+    total = 0
+    for k, (every, steps) in enumerate(((8, 16), (12, 12), (10, 10))):
+        if k:
+            for i in range(len(cfgs)):
+                b.set_limit(i, 1 << 40)  # resume the problems the last run stopped
+        assert b.run(check_every=every, du_tol=0.0, max_steps=steps) == steps
+        total += steps
+    states, nsteps, _, flags = b.state()
+    assert all(n == total for n in nsteps)
+    assert not any(f & (lbm.FLAG_NONFINITE | lbm.FLAG_EOS_DOMAIN) for f in flags)
+    assert b.stats()["node_updates"] == sum(c.nx * c.ny for c in cfgs) * total
+    for i, (c, r0) in enumerate(zip(cfgs, r0s)):
+        _, (rb, ub, vb) = b.observe(i, fields=True)
+        sim = lbm.Simulation(c, to_dev(r0))
+        sim.step(total)
+        os_, (rs, us, vs) = sim.observe(fields=True)
+        sim.close()
+        assert flags[i] == os_["flags"], i
+        for f, g in ((rb, rs), (ub, us), (vb, vs)):
+            assert np.array_equal(f.cpu().numpy(), g.cpu().numpy()), i
+    b.close()
+
+
+def test_automatic_segment_heights_follow_active_lattices():
+    """Problems with tile_y = 0 (FP64 pseudopotential, two steps per launch):
+    while sixteen 512^2 lattices are active their segments are taller than
+    the lowest height (their tiles fill a round of resident workgroups with
+    room to spare); once one is left it runs 8-row segments.  The heights
+    change the tiling only: the survivor and a retired lattice equal the same
+    lattices run alone, bit for bit."""
+    a = 0.25
+    T = cs_T(a, 0.8)
+    rl, rv, _ = th.maxwell(th.CS, a, 4.0, 1.0, T)
+    c = lbm.Config(512, 512, 0, lbm.EOS_CS, a, 4.0, 1.0, T, sigma_li=0.1,
+                   kappa_p=0.9).with_launch(256, 0, 0)
+    n = 16
+    r0s = [inputs.spinodal(512, 512, 0.5 * (rl + rv), 0.01, seed=40 + k) for k in range(n)]
+    b = lbm.Batch([c] * n, [to_dev(r) for r in r0s])
+    assert b.run(check_every=10, du_tol=0.0, max_steps=20) == 20
+    start = [b.launch_info(i) for i in range(n)]
+    assert all(s["steps_per_launch"] == 2 and s["strip"] == 256 for s in start)
+    seg0 = start[0]["segment"]
+    assert seg0 in (16, 32, 64, 128) and all(s["segment"] == seg0 for s in start)
+    assert start[0]["workgroups"] == 2 * (512 // seg0)
+    b.set_limit(0, 1 << 40)  # only problem 0 goes on
+    assert b.run(check_every=10, du_tol=0.0, max_steps=20) == 20
+    assert b.launch_info(0)["segment"] == 8 and b.launch_info(1)["segment"] == seg0
+    _, nsteps, _, _ = b.state()
+    assert nsteps[0] == 40 and all(k == 20 for k in nsteps[1:])
+    for i, steps in ((0, 40), (7, 20)):
+        _, (rb, ub, _) = b.observe(i, fields=True)
+        sim = lbm.Simulation(c, to_dev(r0s[i]))
+        sim.step(steps)
+        _, (rs, us, _) = sim.observe(fields=True)
+        sim.close()
+        assert np.array_equal(rb.cpu().numpy(), rs.cpu().numpy()), i
+        assert np.array_equal(ub.cpu().numpy(), us.cpu().numpy()), i
+    b.close()
