@@ -261,8 +261,9 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
  * tiles of all active problems, and runs of steps are captured in a HIP
  * graph.  Problems on 256-column strips whose kernel_flags allow two steps
  * per launch (0, or LBM_KF_TWO_STEP set) form groups of their own that take
- * two steps per launch, except the last two steps of each check interval;
- * results are the same bit for bit.  A problem with tile_y = 0 has its
+ * two steps per launch (free energy: each tile as two 128-column strips),
+ * except the last two to four steps of each check interval; results are the
+ * same bit for bit.  A problem with tile_y = 0 has its
  * segment height chosen again for its group whenever the active problems
  * change (8 to 128 rows: the tallest whose tiles fill about one round of
  * resident workgroups); tile_rounds is ignored in a batch.  Every

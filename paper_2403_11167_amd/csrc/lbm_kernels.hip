@@ -1694,24 +1694,31 @@ void k_batch_step(const BatchTile* __restrict__ tiles, const int* __restrict__ c
 
 // Two steps of every tile in the table (tile_p2 / tile_fe2, BX + 64 threads,
 // the same row schedules and register choices as k_step2_p / k_step2_fe),
-// walking the table as k_batch_step does.  Tiles are the single-step
-// kernel's (strips of BX columns, the problem's segment height), so one table
-// serves both kernels.
-template <int MODEL, int EOS, class S, class C, int BX>
-__global__ __launch_bounds__(BX + 64)
+// walking the table as k_batch_step does.  The table holds the single-step
+// kernel's 256-column tiles, so one table serves both kernels; the
+// free-energy kernel runs 128-column strips (in FP64 the 256-column one fits
+// only two workgroups per CU) and takes each tile as two halves.
+template <int MODEL>
+constexpr int batch2_bx() { return MODEL == MODEL_P ? 256 : 128; }
+
+template <int MODEL, int EOS, class S, class C>
+__global__ __launch_bounds__(batch2_bx<MODEL>() + 64)
 void k_batch_step2(const BatchTile* __restrict__ tiles, const int* __restrict__ count,
                    const InstDesc<C>* __restrict__ inst, int parity) {
-  const int n = *count;
+  constexpr int BX = batch2_bx<MODEL>();
+  constexpr int SPLIT = 256 / BX;
+  const int n = *count * SPLIT;
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
-    const BatchTile bt = tiles[t];
+    const BatchTile bt = tiles[t / SPLIT];
     const InstDesc<C>* d = inst + bt.inst;
+    const int x0 = bt.x0 + (t % SPLIT) * BX;
+    if (x0 >= d->kp.nx) continue;  // the lattice ends in the first half
     const S* src = (const S*)(parity ? d->fB : d->fA);
     S* dst = (S*)(parity ? d->fA : d->fB);
     if constexpr (MODEL == MODEL_P)
-      tile_p2<EOS, S, C, BX, 1, sizeof(S) == 8 ? 1 : 0>(src, dst, d->kp, d->flags, bt.x0, bt.y0);
+      tile_p2<EOS, S, C, BX, 1, sizeof(S) == 8 ? 1 : 0>(src, dst, d->kp, d->flags, x0, bt.y0);
     else
-      tile_fe2<EOS, S, C, BX, 1, sizeof(S) == 4 ? 1 : 0>(src, dst, d->kp, d->flags, bt.x0,
-                                                       bt.y0);
+      tile_fe2<EOS, S, C, BX, 1, sizeof(S) == 4 ? 1 : 0>(src, dst, d->kp, d->flags, x0, bt.y0);
     __syncthreads();  // the next tile reuses the LDS rings
   }
 }
@@ -3065,6 +3072,9 @@ int resident_blocks(K kernel, int bx) {
   return blocks * cus;
 }
 
+// Strips the two-step kernel of a group cuts each table tile into.
+int batch2_split(const lbm_batch::Group& g) { return g.key.model == MODEL_FE ? 2 : 1; }
+
 // Launch kinds of one group: plain step, checking step, two steps.
 enum BatchLaunch { BL_RESIDENT = -2, BL_GRID = -1, BL_PLAIN = 0, BL_CHECK = 1, BL_TWO = 2 };
 
@@ -3077,10 +3087,10 @@ void launch_batch_group(lbm_batch* b, lbm_batch::Group& g, int kind, int parity)
     if (g.resident == 0) g.resident = resident_blocks(k_batch_step<MODEL, EOS, S, C, BX, 1, 0>, BX);
     if constexpr (BX == 256)
       if (g.key.two && g.resident2 == 0)
-        g.resident2 = resident_blocks(k_batch_step2<MODEL, EOS, S, C, BX>, BX + 64);
+        g.resident2 = resident_blocks(k_batch_step2<MODEL, EOS, S, C>, batch2_bx<MODEL>() + 64);
     if (kind == BL_GRID) {
       g.grid = std::max(1, std::min(g.count, g.resident));
-      if (g.key.two) g.grid2 = std::max(1, std::min(g.count, g.resident2));
+      if (g.key.two) g.grid2 = std::max(1, std::min(g.count * batch2_split(g), g.resident2));
     }
     return;
   }
@@ -3094,8 +3104,8 @@ void launch_batch_group(lbm_batch* b, lbm_batch::Group& g, int kind, int parity)
     hipLaunchKernelGGL((k_batch_step<MODEL, EOS, S, C, BX, 1, 0>), dim3(g.grid), dim3(BX), 0,
                        b->launch, tiles, count, desc, parity);
   else if constexpr (BX == 256)
-    hipLaunchKernelGGL((k_batch_step2<MODEL, EOS, S, C, BX>), dim3(g.grid2), dim3(BX + 64), 0,
-                       b->launch, tiles, count, desc, parity);
+    hipLaunchKernelGGL((k_batch_step2<MODEL, EOS, S, C>), dim3(g.grid2),
+                       dim3(batch2_bx<MODEL>() + 64), 0, b->launch, tiles, count, desc, parity);
 }
 
 template <class S, class C>
@@ -3175,13 +3185,14 @@ lbm_status upload_descs(lbm_batch* b, std::vector<char>& host) {
 // lattices remain, shorter ones keep more workgroups busy.
 int batch_group_ly(const lbm_batch* b, const lbm_batch::Group& g, const std::vector<int>& act) {
   const int64_t G = g.key.two ? g.resident2 : g.resident;
+  const int64_t split = g.key.two ? batch2_split(g) : 1;
   for (int ly : kBatchLY) {
     int64_t T = 0;
     for (int i : act) {
       const lbm_ctx* c = b->inst[i].ctx;
       T += (int64_t)c->nstrips * (b->inst[i].auto_ly ? (c->p.ny + ly - 1) / ly : c->nseg);
     }
-    if (4 * T >= 3 * G) return ly;
+    if (4 * T * split >= 3 * G) return ly;
   }
   return kBatchMinLY;
 }
@@ -3299,7 +3310,7 @@ bool grids_mismatched(const lbm_batch* b) {
   for (const auto& g : b->groups) {
     if (g.count == 0) continue;
     if (off(g.count, g.grid, g.resident)) return true;
-    if (g.key.two && off(g.count, g.grid2, g.resident2)) return true;
+    if (g.key.two && off(g.count * batch2_split(g), g.grid2, g.resident2)) return true;
   }
   return false;
 }
