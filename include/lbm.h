@@ -265,7 +265,7 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_workspace, size_t bytes,
  * except the last two to four steps of each check interval; results are the
  * same bit for bit.  A problem with tile_y = 0 has its
  * segment height chosen again for its group whenever the active problems
- * change (8 to 128 rows: the tallest whose tiles fill about one round of
+ * change (4 to 128 rows: the tallest whose tiles fill about one round of
  * resident workgroups); tile_rounds is ignored in a batch.  Every
  * check_every steps a checking step measures, per problem,
  * max |u(t) - u(t - check_every)|; a problem retires as converged when that

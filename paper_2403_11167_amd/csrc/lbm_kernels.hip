@@ -3022,8 +3022,8 @@ struct BatchLayout {
 constexpr int kMaxGroups = 12;  // 2 models x 2 EOS x (64, 256, 256 two-step)
 // Automatic segment heights in a batch: the lowest, which sizes the tile
 // tables, and the candidates above it, tallest first.
-constexpr int kBatchMinLY = 8;
-constexpr int kBatchLY[] = {128, 64, 32, 16};
+constexpr int kBatchMinLY = 4;
+constexpr int kBatchLY[] = {128, 64, 32, 16, 8};
 
 BatchLayout make_batch_layout(int n, const lbm_params* p) {
   BatchLayout B;
