@@ -18,13 +18,17 @@
 //                  gradient is deterministic;
 //   k_mlp_adam     one elementwise Adam update.
 // The network is ~34k parameters: every launch is latency-bound, not bound
-// by HBM or the matrix units, so the products run on the vector ALUs.
+// by HBM or the matrix units.
 //
 // BF16 mode rounds every product operand (layer inputs and weights) to
 // bfloat16, round to nearest even; products of two bfloat16 values are exact
-// in FP32 and all sums accumulate in FP32.  Biases and back-propagated
-// errors are not rounded; the weight rounding is treated as the identity in
-// the gradient.
+// in FP32 and all sums accumulate in FP32.  Its two 128 x 128 hidden layers
+// run on the matrix cores (v_mfma_f32_16x16x16_bf16, hidden_mfma), in the
+// forward pass of inference and of training; the 4-wide input and output
+// layers and all FP32-mode products run on the vector ALUs.  Biases and
+// back-propagated errors are not rounded (so the backward products stay on
+// the vector ALUs in FP32); the weight rounding is treated as the identity
+// in the gradient.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -77,12 +81,58 @@ __device__ __forceinline__ float gelu_d(float z) {
          z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Bit pattern of a float that is already a bfloat16 value (low half zero).
+__device__ __forceinline__ short bf16_bits(float v) {
+  return (short)(__float_as_uint(v) >> 16);
+}
+
+// One 128 -> 128 hidden layer of a 16-sample tile on the matrix cores
+// (BF16 mode): Z = A W + b with A the tile's rounded activations [16][128]
+// and W the layer's weights [128][128] (row k, column j), rounded to
+// bfloat16 as they are read; products of bfloat16 values are exact and the
+// sums accumulate in FP32.  v_mfma_f32_16x16x16_bf16 multiplies a 16 x 16
+// block of A by a 16 x 16 block of W: lane l supplies A[l % 16][4 (l / 16)
+// + v] and W[4 (l / 16) + v][l % 16] (v = 0..3, offsets within the blocks)
+// and receives Z[4 (l / 16) + v][l % 16].  Each of the four wavefronts
+// computes two 16-column blocks of Z over the eight 16-row blocks of W.
+__device__ __forceinline__ void hidden_mfma(const float* __restrict__ W, const float* __restrict__ bias,
+                            const float (*a)[H], float (*z)[H], float (*an)[H]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int j = (2 * wv + nb) * 16 + r;
+    const float b = bias[j];
+    f32x4 acc = {b, b, b, b};
+#pragma unroll
+    for (int kb = 0; kb < H / 16; ++kb) {
+      const int k0 = kb * 16 + 4 * q;
+      bf16x4 av, wv4;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        av[v] = bf16_bits(a[r][k0 + v]);
+        wv4[v] = bf16_bits(bf16r(W[(k0 + v) * H + j]));
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, wv4, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * q + v;
+      z[i][j] = acc[v];
+      an[i][j] = bf16r(gelu(acc[v]));
+    }
+  }
+}
+
 // Forward pass of one tile.  s_a0: [TS][NI] rounded inputs (already set);
 // s_z: [3][TS][H] pre-activations; s_a: [3][TS][H] rounded activations;
 // s_o: [TS][NO] outputs in normalised log space.  Sample rows >= nv hold
 // zero inputs and finite values that the callers ignore.
 template <int BF>
-__device__ void forward_tile(const float* __restrict__ P, const float (*s_a0)[NI],
+__device__ __forceinline__ void forward_tile(const float* __restrict__ P, const float (*s_a0)[NI],
                              float (*s_z)[TS][H], float (*s_a)[TS][H], float (*s_o)[NO]) {
   const int t = threadIdx.x;
   const int j = t & (H - 1), sh = (t >> 7) * HALF;
@@ -106,6 +156,11 @@ __device__ void forward_tile(const float* __restrict__ P, const float (*s_a0)[NI
   __syncthreads();
   for (int l = 1; l < 3; ++l) {
     const float* W = P + (l == 1 ? OFF_W2 : OFF_W3);
+    if constexpr (BF) {
+      hidden_mfma(W, P + (l == 1 ? OFF_B2 : OFF_B3), s_a[l - 1], s_z[l], s_a[l]);
+      __syncthreads();
+      continue;
+    }
     float acc[HALF];
     const float b = P[(l == 1 ? OFF_B2 : OFF_B3) + j];
 #pragma unroll
