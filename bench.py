@@ -41,7 +41,7 @@ CS = dict(a=0.25, b=4.0, R=1.0)
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("lbm_kernels.hip",):
+    for name in ("lbm_kernels.hip", "lbm_math.h"):
         with open(os.path.join(ROOT, "paper_2403_11167_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
