@@ -220,13 +220,11 @@ def build_problems(tuples, sizes, precision, guesses=None, tiles=None):
 
 
 # (strip width, segment height); height 0: chosen by the batch for each
-# group from its active lattices at every retirement
-TILE_CANDIDATES = ((64, 0), (64, 8), (64, 16), (64, 32), (256, 0), (256, 8), (256, 16),
-                   (256, 32), (256, 64))
-# a fixed height must beat the automatic one by this factor to be chosen:
-# the timing covers the full class, while the automatic height also follows
-# the class as its lattices retire
-AUTO_MARGIN = 0.95
+# group from its active lattices at every retirement.  Fixed heights are
+# not candidates: timed on a full class, the best of them beats the
+# automatic height by a few per cent, but it stays when the class has
+# retired down to a few lattices, where it is several times slower.
+TILE_CANDIDATES = ((64, 0), (256, 0))
 
 
 def class_counts(tuples, sizes):
@@ -240,49 +238,50 @@ def class_counts(tuples, sizes):
     return out
 
 
-def autotune_batch_tiles(precision=lbm.FP32_SHIFTED, sizes=SIZES, steps=40, nodes=1 << 20,
+def autotune_batch_tiles(precision=lbm.FP32_SHIFTED, sizes=SIZES, steps=100, nodes=1 << 20,
                          counts=None, log=None):
-    """The batch tile shape (tile_x, tile_y) of each size class (model, L x L)
-    of the calibration: for every class, a batch of flat-interface lattices
-    of that class (counts[(model, L, L)] of them when given, the class's
-    share of the batch to be run, else about `nodes` nodes; mid-range tuple
-    Tr = 0.75, w = 5, kappa = 1.25) runs `steps` lockstep steps per candidate
-    shape, timed by the batch's own GPU clock (lbm_batch_stats).  Strips of
-    256 columns are tried where L >= 256 (they take two steps per launch).
-    The automatic height (0) is kept unless a fixed one takes less than
-    AUTO_MARGIN of its GPU time per node update.  Returns
-    {(model, L, L): (tile_x, tile_y)} and the timings."""
+    """The batch tile shape (tile_x, tile_y) of each size class (model, nx, ny)
+    of a calibration: for every class, a batch of flat-interface lattices of
+    that class (counts[class] of them when given, the class's share of the
+    batch to be run; else the classes (model, L, L) for L in sizes, about
+    `nodes` nodes each; mid-range tuple Tr = 0.75, w = 5, kappa = 1.25) runs
+    `steps` lockstep steps per candidate shape in one check interval (as in
+    a run, the last steps of an interval are single steps), timed by the
+    batch's own GPU clock (lbm_batch_stats).  Strips of 256 columns (two
+    steps per launch) are tried where nx >= 128; the least GPU time per node
+    update wins.  Returns {(model, nx, ny): (tile_x, tile_y)} and the
+    timings."""
     import torch
     say = log or (lambda *a: None)
     dev = torch.device("cuda:0")
+    if counts:
+        classes = sorted(counts)
+    else:
+        classes = [(m, L, L) for m in (lbm.MODEL_P, lbm.MODEL_FE) for L in sizes]
     best, table = {}, []
-    for model in (lbm.MODEL_P, lbm.MODEL_FE):
+    for model, nx, ny in classes:
         t = Tuple4(model, 0.75, 5.0, 1.25)
         rl, rv, W = initial_guess(t)
-        for L in sizes:
-            n = (counts or {}).get((model, L, L), 0) or max(2, nodes // (L * L))
-            rho = torch.from_numpy(flat_rho0(L, L, rl, rv, W)).to(dev)
-            timings = []
-            for tx, ty in TILE_CANDIDATES:
-                if (tx == 256 and L < 256) or ty > L:
-                    continue
-                cfg = model_config(t, L, L, precision).with_launch(tx, ty, 0)
-                b = lbm.Batch([cfg] * n, [rho] * n)
-                b.run(check_every=steps // 2, du_tol=0.0, max_steps=steps)
-                st = b.stats()
-                b.close()
-                timings.append((st["gpu_ms"] * 1e6 / max(st["node_updates"], 1), tx, ty))
-            ns, tx, ty = min(timings)
-            if ty != 0:
-                auto = min((v, a, c) for v, a, c in timings if c == 0)
-                if ns >= AUTO_MARGIN * auto[0]:
-                    ns, tx, ty = auto
-            best[(model, L, L)] = (tx, ty)
-            table.append(dict(model="P" if model == lbm.MODEL_P else "FE", L=L, lattices=n,
-                              tile_x=tx, tile_y=ty, ns_per_node_update=ns,
-                              candidates={f"{a}x{c}": v for v, a, c in timings}))
-            say(f"batch tiles: {'P' if model == lbm.MODEL_P else 'FE'} L={L} ({n} lattices): "
-                f"{tx}x{ty or 'auto'}, {ns:.4f} ns per node update")
+        n = (counts or {}).get((model, nx, ny), 0) or max(2, nodes // (nx * ny))
+        rho = torch.from_numpy(flat_rho0(nx, ny, rl, rv, W)).to(dev)
+        timings = []
+        for tx, ty in TILE_CANDIDATES:
+            if (tx == 256 and nx < 128) or ty > ny:
+                continue
+            cfg = model_config(t, nx, ny, precision).with_launch(tx, ty, 0)
+            b = lbm.Batch([cfg] * n, [rho] * n)
+            b.run(check_every=steps, du_tol=0.0, max_steps=steps)
+            st = b.stats()
+            b.close()
+            timings.append((st["gpu_ms"] * 1e6 / max(st["node_updates"], 1), tx, ty))
+        ns, tx, ty = min(timings)
+        best[(model, nx, ny)] = (tx, ty)
+        name = "P" if model == lbm.MODEL_P else "FE"
+        table.append(dict(model=name, nx=nx, ny=ny, lattices=n, tile_x=tx, tile_y=ty,
+                          ns_per_node_update=ns,
+                          candidates={f"{a}x{c}": v for v, a, c in timings}))
+        say(f"batch tiles: {name} {nx}x{ny} ({n} lattices): {tx}x{ty or 'auto'}, "
+            f"{ns:.4f} ns per node update")
     return best, table
 
 
@@ -519,7 +518,8 @@ def valid(labels):
 def training_set(n_tuples: int, seed: int, size=(64, 8, 128), **kw):
     """Calibration labels for n_tuples sampled tuples on small lattices
     (flat 64 x 8, droplet 128 x 128 by default): (features, targets, info)
-    with only valid tuples kept."""
+    with only valid tuples kept.  Keyword arguments go to run_calibration
+    (tiles: from autotune_batch_tiles on class_counts of the same tuples)."""
     tuples = sample_tuples(n_tuples, seed)
     labels, info = run_calibration(tuples, [size] * n_tuples, **kw)
     m = valid(labels)
@@ -603,7 +603,13 @@ def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_
     import torch
     say = log or (lambda *a: None)
     t0 = time.perf_counter()
-    x, y, info_t = training_set(n_train, seed_train, size=train_size, max_steps=max_steps)
+    train_tiles, train_tile_table = autotune_batch_tiles(
+        counts=class_counts(sample_tuples(n_train, seed_train), [train_size] * n_train), log=say)
+    train_tune_s = time.perf_counter() - t0
+    say(f"training set tiles tuned in {train_tune_s:.1f} s")
+    t0 = time.perf_counter()
+    x, y, info_t = training_set(n_train, seed_train, size=train_size, max_steps=max_steps,
+                                tiles=train_tiles)
     gen_s = time.perf_counter() - t0
     say(f"training set: {len(x)} valid of {n_train} tuples in {gen_s:.1f} s")
     sur = lbm.Surrogate(inputs.mlp_initial_params(0))
@@ -648,6 +654,7 @@ def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_
                       precision="fp32_shifted"),
         training=dict(tuples=n_train, valid=int(len(x)), lattices=2 * n_train,
                       size=list(train_size), generation_s=gen_s, train_s=train_s,
+                      tile_tuning_s=train_tune_s, tiles=train_tile_table,
                       epochs=epochs, loss_first=float(losses[0]), loss_last=float(losses[-1])),
         plain=dict(seconds=inf_p["seconds"], tuples_converged=inf_p["converged_units"],
                    tuples_per_s=inf_p["units_per_second"], lockstep_steps=inf_p["steps"],

@@ -1697,7 +1697,9 @@ void k_batch_step(const BatchTile* __restrict__ tiles, const int* __restrict__ c
 // walking the table as k_batch_step does.  The table holds the single-step
 // kernel's 256-column tiles, so one table serves both kernels; the
 // free-energy kernel runs 128-column strips (in FP64 the 256-column one fits
-// only two workgroups per CU) and takes each tile as two halves.
+// only two workgroups per CU) and takes each tile as two halves: the first
+// halves of all tiles, then the second halves, so that the halves a narrow
+// lattice leaves empty fall on every workgroup alike.
 template <int MODEL>
 constexpr int batch2_bx() { return MODEL == MODEL_P ? 256 : 128; }
 
@@ -1707,11 +1709,12 @@ void k_batch_step2(const BatchTile* __restrict__ tiles, const int* __restrict__ 
                    const InstDesc<C>* __restrict__ inst, int parity) {
   constexpr int BX = batch2_bx<MODEL>();
   constexpr int SPLIT = 256 / BX;
-  const int n = *count * SPLIT;
+  const int nt = *count;
+  const int n = nt * SPLIT;
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
-    const BatchTile bt = tiles[t / SPLIT];
+    const BatchTile bt = tiles[t % nt];
     const InstDesc<C>* d = inst + bt.inst;
-    const int x0 = bt.x0 + (t % SPLIT) * BX;
+    const int x0 = bt.x0 + (t / nt) * BX;
     if (x0 >= d->kp.nx) continue;  // the lattice ends in the first half
     const S* src = (const S*)(parity ? d->fB : d->fA);
     S* dst = (S*)(parity ? d->fA : d->fB);
@@ -3185,14 +3188,15 @@ lbm_status upload_descs(lbm_batch* b, std::vector<char>& host) {
 // lattices remain, shorter ones keep more workgroups busy.
 int batch_group_ly(const lbm_batch* b, const lbm_batch::Group& g, const std::vector<int>& act) {
   const int64_t G = g.key.two ? g.resident2 : g.resident;
-  const int64_t split = g.key.two ? batch2_split(g) : 1;
+  const int sx = g.key.two ? 256 / batch2_split(g) : g.key.bx;  // columns per launched strip
   for (int ly : kBatchLY) {
     int64_t T = 0;
     for (int i : act) {
       const lbm_ctx* c = b->inst[i].ctx;
-      T += (int64_t)c->nstrips * (b->inst[i].auto_ly ? (c->p.ny + ly - 1) / ly : c->nseg);
+      const int strips = (c->p.nx + sx - 1) / sx;  // strips that hold lattice columns
+      T += (int64_t)strips * (b->inst[i].auto_ly ? (c->p.ny + ly - 1) / ly : c->nseg);
     }
-    if (4 * T * split >= 3 * G) return ly;
+    if (4 * T >= 3 * G) return ly;
   }
   return kBatchMinLY;
 }
