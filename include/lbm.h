@@ -331,9 +331,11 @@ lbm_status lbm_batch_stats(const lbm_batch* b, int64_t* node_updates, double* gp
 
 /* The launch shape of problem i in the batch (not part of the paper's
  * method): steps_per_launch 2 when its group takes two steps per launch,
- * strip and threads of that kernel, segment its current segment height
- * (with tile_y = 0 it may change whenever the active problems change), and
- * workgroups its number of tiles.  Host only. */
+ * strip and threads of that kernel (a two-step free-energy group runs each
+ * 256-column tile as two 128-column strips), segment its current segment
+ * height (with tile_y = 0 it may change whenever the active problems
+ * change), and workgroups the strip-by-segment tiles of that kernel that
+ * hold its columns.  Host only. */
 lbm_status lbm_batch_launch_info(const lbm_batch* b, int32_t i, lbm_launch* out);
 
 /* Per-problem state (LBM_BATCH_*), steps taken, last measured max |du| and

@@ -3667,11 +3667,13 @@ lbm_status lbm_batch_launch_info(const lbm_batch* b, int32_t i, lbm_launch* out)
   memset(out, 0, sizeof(*out));
   const lbm_ctx* c = b->inst[i].ctx;
   const int two = batch_two(c);
+  // a two-step free-energy group runs each 256-column tile as two strips
+  const int strip = two && c->p.model == LBM_MODEL_FE ? 128 : c->lc.bx;
   out->steps_per_launch = two ? 2 : 1;
-  out->strip = c->lc.bx;
-  out->threads = two ? c->lc.bx + 64 : c->lc.bx;
+  out->strip = strip;
+  out->threads = two ? strip + 64 : strip;
   out->segment = c->lc.ly;
-  out->workgroups = c->nstrips * c->nseg;
+  out->workgroups = (c->p.nx + strip - 1) / strip * c->nseg;
   return LBM_OK;
 }
 

@@ -312,6 +312,12 @@ def test_two_step_groups_equal_single_runs(precision):
     cfgs = [c for c, _, _ in cases]
     r0s = [inputs.spinodal(c.nx, c.ny, m, 0.01, seed=s) for c, m, s in cases]
     b = lbm.Batch(cfgs, [to_dev(r) for r in r0s])
+    # (steps per launch, strip, threads, workgroups) of each problem's kernel
+    shapes = [(2, 256, 320, 5), (2, 128, 192, 3 * 2), (2, 256, 320, 2 * 3), (1, 256, 256, 4),
+              (1, 64, 64, 6)]
+    for i, want in enumerate(shapes):
+        li = b.launch_info(i)
+        assert (li["steps_per_launch"], li["strip"], li["threads"], li["workgroups"]) == want, i
     total = 0
     for k, (every, steps) in enumerate(((8, 16), (12, 12), (10, 10))):
         if k:
