@@ -152,6 +152,39 @@ def load_traffic(variant: str):
     return k.get("bytes_per_launch"), name
 
 
+def batch_roofline(dev, L=512, n=64, steps=200):
+    """The batch kernels on the calibration's largest class: n flat-interface
+    lattices of L x L per model (as many nodes as the 4096^2 lattice),
+    FP32-shifted, 256-column strips, automatic segment heights, one check
+    interval of `steps` lockstep steps after one of warm-up (which also fixes
+    the heights), timed by the batch's own GPU clock.  Algorithmic bytes: 72
+    per node update."""
+    import torch
+    from paper_2403_11167_amd import calibration as cal, lbm
+    out = []
+    for model in (lbm.MODEL_P, lbm.MODEL_FE):
+        t = cal.Tuple4(model, 0.75, 5.0, 1.25)
+        rl, rv, W = cal.initial_guess(t)
+        rho = torch.from_numpy(cal.flat_rho0(L, L, rl, rv, W)).to(dev)
+        cfg = cal.model_config(t, L, L, lbm.FP32_SHIFTED).with_launch(256, 0, 0)
+        b = lbm.Batch([cfg] * n, [rho] * n)
+        b.run(check_every=steps, du_tol=0.0, max_steps=steps)
+        for i in range(n):
+            b.set_limit(i, 1 << 40)  # resume after the warm-up interval
+        s0 = b.stats()
+        b.run(check_every=steps, du_tol=0.0, max_steps=steps)
+        s1 = b.stats()
+        li = b.launch_info(0)
+        b.close()
+        nu = s1["node_updates"] - s0["node_updates"]
+        sec = (s1["gpu_ms"] - s0["gpu_ms"]) * 1e-3
+        gbs = 72 * nu / sec / 1e9
+        out.append(dict(model="P" if model == lbm.MODEL_P else "FE", lattices=n, L=L,
+                        steps=steps, node_updates=nu, gpu_s=sec, ns_per_node_update=sec * 1e9 / nu,
+                        hbm_gbs_algorithmic=gbs, frac_of_8tbs=gbs / 8000.0, launch=li))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +205,8 @@ def main():
     ap.add_argument("--calib-held", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--batch-roofline", action="store_true",
+                    help="only time the batch kernels: 64 lattices of 512^2 per model")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -195,6 +230,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": nbytes, "launches": 3}))
+        return
+
+    if args.batch_roofline:
+        for line in batch_roofline(dev):
+            print(json.dumps(line))
         return
 
     cfg_factory, rho0, desc = workload(args.workload, args.n)
