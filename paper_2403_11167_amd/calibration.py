@@ -31,6 +31,7 @@ Seeded initial profiles use predicted (rho_l, rho_v, W) instead.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -81,11 +82,42 @@ def kappa_fe(t: Tuple4) -> float:
     return A * t.kappa
 
 
+_P_MATCH: dict = {}
+
+
+def p_match(Tr: float, kfe: float, w: float):
+    """(sigma^Li, kappa^P, kappa^Li) of a pseudopotential tuple (lbm.match_p_to_fe,
+    kept per tuple: its planar-theory tabulations take milliseconds, and a
+    tuple's flat and droplet lattices share the result)."""
+    key = (Tr, kfe, w)
+    if key not in _P_MATCH:
+        _P_MATCH[key] = lbm.match_p_to_fe(EOS, A, B, RGAS, Tr * critical_T(), kfe, w)
+    return _P_MATCH[key]
+
+
+def prefill_p_match(tuples, workers: int = 16):
+    """Compute p_match for the pseudopotential tuples not computed yet on a
+    thread pool: the library call runs without the interpreter lock and
+    has no shared state, and each result depends on its tuple alone."""
+    from concurrent.futures import ThreadPoolExecutor
+    keys = sorted({(t.Tr, kappa_fe(t), t.w) for t in tuples if t.model == lbm.MODEL_P}
+                  - set(_P_MATCH))
+    if len(keys) < 2:
+        return
+    lib = lbm.lib()  # load the library before the threads call it
+    assert lib is not None
+    Tc = critical_T()
+    with ThreadPoolExecutor(max_workers=max(1, min(workers, os.cpu_count() or 1))) as ex:
+        res = list(ex.map(lambda k: lbm.match_p_to_fe(EOS, A, B, RGAS, k[0] * Tc, k[1], k[2]),
+                          keys))
+    _P_MATCH.update(zip(keys, res))
+
+
 def model_config(t: Tuple4, nx: int, ny: int, precision: int) -> lbm.Config:
     T = t.Tr * critical_T()
     tau = [1.0] * 9
     if t.model == lbm.MODEL_P:
-        sig, kp, kli = lbm.match_p_to_fe(EOS, A, B, RGAS, T, kappa_fe(t), t.w)
+        sig, kp, kli = p_match(t.Tr, kappa_fe(t), t.w)
         tau[4] = tau[6] = 1.0 / 1.99
         return lbm.Config(nx, ny, lbm.MODEL_P, EOS, A, B, RGAS, T, tau=tau, sigma_li=sig,
                           kappa_p=kp, kappa_li=kli, precision=precision)
@@ -196,6 +228,7 @@ def build_problems(tuples, sizes, precision, guesses=None, tiles=None):
     (flat nx, flat ny, droplet L).  guesses: per-tuple (rho_l, rho_v, W)
     (None: plain guesses).  tiles: batch tile shape per size class (see
     autotune_batch_tiles)."""
+    prefill_p_match(tuples)
     cfgs, rho0s, meta = [], [], []
     for k, (t, size) in enumerate(zip(tuples, sizes)):
         g = guesses[k] if guesses is not None else initial_guess(t)

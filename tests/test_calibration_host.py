@@ -67,3 +67,20 @@ def test_class_counts_cover_both_lattices_of_each_tuple():
     held = cal.sample_tuples(64, 6)
     sizes = cal.sample_sizes(64, 6)
     assert sum(cal.class_counts(held, sizes).values()) == 2 * 64
+
+
+def test_parallel_p_match_equals_serial_calls():
+    """The pseudopotential matching of a tuple (sigma^Li, kappa^P, kappa^Li,
+    App. B and C) computed on a thread pool ahead of the configs equals the
+    library call made directly, for every tuple."""
+    tuples = [t for t in cal.sample_tuples(40, 21) if t.model == lbm.MODEL_P]
+    assert len(tuples) > 5
+    cal._P_MATCH.clear()
+    cal.prefill_p_match(tuples, workers=4)
+    for t in tuples:
+        direct = lbm.match_p_to_fe(cal.EOS, cal.A, cal.B, cal.RGAS, t.Tr * cal.critical_T(),
+                                   cal.kappa_fe(t), t.w)
+        assert cal.p_match(t.Tr, cal.kappa_fe(t), t.w) == direct
+    cfg = cal.model_config(tuples[0], 64, 64, lbm.FP32_SHIFTED)
+    assert (cfg.sigma_li, cfg.kappa_p, cfg.kappa_li) == cal.p_match(
+        tuples[0].Tr, cal.kappa_fe(tuples[0]), tuples[0].w)
