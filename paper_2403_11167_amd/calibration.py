@@ -350,14 +350,16 @@ def run_calibration(tuples, sizes, precision=lbm.FP32_SHIFTED, guesses=None,
     """Run the flat + droplet pair of every tuple to equilibrium in one batch.
     Returns (labels, info): labels[k] = dict(rho_l, rho_v, W, sigma, ok) and
     info = dict(seconds, steps, states, steps_per_problem, ...).  The timed
-    region covers building the batch (initial populations on the device)
-    and running it to retirement."""
+    region covers everything from the tuples to the labels, as in
+    run_seeded_calibration: the configs and initial fields, the batch
+    (initial populations on the device), the run to retirement and the
+    measurement of the labels."""
     import time
 
     import torch
     dev = torch.device("cuda:0")
-    cfgs, rho0s, meta = build_problems(tuples, sizes, precision, guesses, tiles)
     t0 = time.perf_counter()
+    cfgs, rho0s, meta = build_problems(tuples, sizes, precision, guesses, tiles)
     batch = lbm.Batch(cfgs, [torch.from_numpy(r).to(dev) for r in rho0s])
     pair_units(batch, meta)
     tr = time.perf_counter()
