@@ -109,6 +109,28 @@ def test_init_rejects_missing_buffers_without_device_work():
     assert L.lbm_get_populations(None, None) == lbm.ERR_INVALID_ARG
 
 
+def test_batch_entry_points_reject_null_handles_without_device_work():
+    L = lbm.lib()
+    out = lbm.Launch()
+    nu, ms, ch = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    assert L.lbm_batch_launch_info(None, 0, ctypes.byref(out)) == lbm.ERR_INVALID_ARG
+    assert L.lbm_batch_stats(None, ctypes.byref(nu), ctypes.byref(ms),
+                             ctypes.byref(ch)) == lbm.ERR_INVALID_ARG
+    assert L.lbm_batch_run(None, 200, 1e-9, 10, None) == lbm.ERR_INVALID_ARG
+    assert L.lbm_batch_set_limit(None, 0, 10) == lbm.ERR_INVALID_ARG
+    assert L.lbm_batch_set_partner(None, 0, 1) == lbm.ERR_INVALID_ARG
+    assert L.lbm_batch_destroy(None) == lbm.ERR_INVALID_ARG
+    # a batch of no problems, or of one whose workspace is missing, is refused
+    p = base_cfg().c_params()
+    b = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t()
+    assert L.lbm_batch_workspace_bytes(0, ctypes.byref(p), ctypes.byref(nbytes)) == \
+        lbm.ERR_INVALID_ARG
+    ptrs = (ctypes.c_void_p * 1)(8)
+    assert L.lbm_batch_create(1, ctypes.byref(p), ptrs, None, 0, None,
+                              ctypes.byref(b)) == lbm.ERR_WORKSPACE
+
+
 # ---- host thermodynamics (C++) against the oracle theory (numpy/scipy) -------
 @pytest.mark.parametrize("eos,a,b", [(lbm.EOS_CS, 1.0, 4.0), (lbm.EOS_CS, 0.25, 4.0),
                                      (lbm.EOS_VDW, 9 / 49, 2 / 21)])
