@@ -593,6 +593,23 @@ def compare(labels_a, labels_b):
     return {k: rel[:, i] for i, k in enumerate(("rho_l", "rho_v", "sigma", "W"))}, m
 
 
+def by_size(rel, m, sizes):
+    """Agreement of the labels compared by `compare` (rel, m) per lattice size
+    L of the tuple, and over L >= 128: the 64^2 droplets (R = L/5 = 12.8)
+    are only a few interface widths across."""
+    L = np.array([_shape(v)[2] for v in sizes])[m]
+
+    def part(sel):
+        return dict(tuples=int(sel.sum()),
+                    **{f"{k}_within_{int(100 * t)}pct": (float(np.mean(rel[k][sel] <= t))
+                                                         if sel.any() else None)
+                       for k, t in (("rho_l", 0.01), ("rho_v", 0.01), ("sigma", 0.03),
+                                    ("sigma", 0.01), ("W", 0.03))})
+    out = {str(v): part(L == v) for v in sorted(set(L.tolist()))}
+    out["128_and_up"] = part(L >= 128)
+    return out
+
+
 def _stats(rel, tol):
     if len(rel) == 0:
         return dict(median=None, p95=None, max=None, frac_within=None, tol=tol)
@@ -678,6 +695,11 @@ def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_
     say(f"seeded: {inf_s['seconds']:.1f} s, {inf_s['converged_units']} tuples, "
         f"{inf_s['accepted']} accepted after verification")
     rel, m = compare(lab_p, lab_s)
+    big = by_size(rel, m, sizes)["128_and_up"]
+    if big["tuples"]:
+        say(f"seeded vs plain, L >= 128 ({big['tuples']} tuples): sigma within 3 %: "
+            f"{100 * big['sigma_within_3pct']:.1f} %, rho_v within 1 %: "
+            f"{100 * big['rho_v_within_1pct']:.1f} %")
     pred = pred_only
     yp = targets(lab_p)
     mp = valid(lab_p)
@@ -710,6 +732,8 @@ def benchmark(n_train: int = 2000, n_held: int = 256, seed_train: int = 5, seed_
                                  "inputs, FP32 accumulate) in place of the plain runs; "
                                  "accuracy in surrogate_vs_plain"),
         seeded_vs_plain={k: _stats(rel[k], TOLERANCES[k]) for k in names},
+        seeded_vs_plain_by_size=by_size(rel, m, sizes),
+        plain_vs_plain_by_size=by_size(rel_pp, m_pp, sizes),
         plain_vs_plain=dict(
             note="the plain calibration run a second time from starts with 1.6 times wider "
                  "interfaces: how reproducible the labels of the method itself are",

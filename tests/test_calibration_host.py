@@ -84,3 +84,20 @@ def test_parallel_p_match_equals_serial_calls():
     cfg = cal.model_config(tuples[0], 64, 64, lbm.FP32_SHIFTED)
     assert (cfg.sigma_li, cfg.kappa_p, cfg.kappa_li) == cal.p_match(
         tuples[0].Tr, cal.kappa_fe(tuples[0]), tuples[0].w)
+
+
+def test_agreement_by_lattice_size():
+    """by_size splits the label comparison by each tuple's lattice size and
+    adds L >= 128; fractions count relative differences within tolerance."""
+    def lab(s):
+        return dict(rho_l=5.0, rho_v=0.5, W=6.0, sigma=s, ok=True)
+    a = [lab(1.0), lab(1.0), lab(1.0), lab(1.0)]
+    b = [lab(1.005), lab(1.05), lab(1.0), lab(1.02)]
+    b[2]["ok"] = False
+    rel, m = cal.compare(a, b)
+    out = cal.by_size(rel, m, [64, 64, 128, 256])
+    assert out["64"]["tuples"] == 2 and out["64"]["sigma_within_3pct"] == 0.5
+    assert out["64"]["sigma_within_1pct"] == 0.5 and out["64"]["rho_v_within_1pct"] == 1.0
+    assert "128" not in out  # its only tuple is not valid in both
+    assert out["256"]["sigma_within_3pct"] == 1.0 and out["256"]["sigma_within_1pct"] == 0.0
+    assert out["128_and_up"]["tuples"] == 1
